@@ -1,0 +1,488 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: numbers the
+paper prints (cohesive energy, lattice constant, elastic constants), closed
+forms for symmetric structures, special cases that reduce to textbook pair
+potentials, finite differences, invariances and a brute-force neighbour loop.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import tersoff as T
+from oracle.neighbors import neighbor_list, neighbor_list_naive
+
+EV_A3_TO_GPA = 160.21766208
+R1, R2 = 2.8, 3.2
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def table2(golden):
+    t = golden["table2_parameters"]
+    return (t["D0_eV"], t["alpha_per_A"], t["r0_A"], t["beta"], t["n"], t["h"])
+
+
+def energy(pos, cell, x):
+    return float(T.evaluate(pos, cell, x, R1, R2)["E"][0])
+
+
+def test_table2_fixture_matches_workload_constants(golden):
+    assert table2(golden) == W.TABLE2_X
+    t = golden["table2_parameters"]
+    assert (t["R1_A"], t["R2_A"]) == (W.TABLE2_R1, W.TABLE2_R2)
+    lo, hi = np.asarray(W.PARAM_LO), np.asarray(W.PARAM_HI)
+    assert np.all(lo < np.asarray(W.TABLE2_X)) and np.all(np.asarray(W.TABLE2_X) < hi)
+
+
+# ----------------------------------------------------------------------------
+# Closed forms and printed values
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("a", [5.25, 5.43, 5.60])
+def test_diamond_lattice_closed_form(a):
+    """Perfect diamond: four neighbours at sqrt(3)a/4 with cos(theta) = -1/3."""
+    xs = [W.TABLE2_X] + list(W.draw_params(rng(11), 4))
+    pos, cell = W.diamond(2, 2, 2, a)
+    for x in xs:
+        out = T.evaluate(pos, cell, x, R1, R2)
+        e = out["E"][0] / 64
+        ref = T.diamond_closed_form(x, a)
+        assert abs(e - ref) <= 1e-13 * abs(ref)
+        assert np.abs(out["F"]).max() <= 1e-12
+        assert out["n_bonds"] == 256 and out["n_triplets"] == 768
+
+
+def test_diamond_virial_is_strain_derivative_of_closed_form():
+    """W = -dE/d(eps); for an isotropic strain of perfect diamond
+    W_xx = W_yy = W_zz = -(a/3) de/da * N and the shear parts vanish."""
+    x = W.TABLE2_X
+    a = 5.43
+    pos, cell = W.diamond(2, 2, 2, a)
+    out = T.evaluate(pos, cell, x, R1, R2)
+    h = 1e-6
+    dede = (T.diamond_closed_form(x, a + h) - T.diamond_closed_form(x, a - h)) / (2 * h)
+    expect = -(a / 3.0) * dede * 64
+    assert np.allclose(out["W6"][0, :3], expect, rtol=1e-8)
+    assert np.abs(out["W6"][0, 3:]).max() < 1e-12
+    assert abs(out["W6"][0, 0] / 64 - 0.022103) < 5e-7
+
+
+def _equilibrium(x):
+    from scipy.optimize import minimize_scalar
+    res = minimize_scalar(lambda a: T.diamond_closed_form(x, a), bounds=(5.2, 5.7),
+                          method="bounded", options={"xatol": 1e-9})
+    return res.x, res.fun
+
+
+def test_cohesive_energy_and_lattice_constant_match_paper(golden):
+    """Sec. III.C prints -4.63 eV/atom and 5.434 A for the Table 2 parameters."""
+    x = table2(golden)
+    a0, e0 = _equilibrium(x)
+    # the minimum found on the closed form is also the minimum of the full sum
+    pos, cell = W.diamond(1, 1, 1, a0)
+    assert abs(energy(pos, cell, x) / 8 - e0) < 1e-12
+    c = golden["cohesive_energy"]
+    assert round(e0, c["printed_decimals"]) == c["E_c_eV_per_atom"]
+    # 5.43342 A from the printed six-digit parameters: within one unit of the
+    # printed last digit (the parameters themselves are rounded in Table 2)
+    assert abs(a0 - c["a_A"]) <= 10.0 ** -c["a_printed_decimals"]
+
+
+def _stress(pos, cell, x):
+    out = T.evaluate(pos, cell, x, R1, R2)
+    Wt = np.zeros((3, 3))
+    for (m, n), v in zip(T.VIRIAL6, out["W6"][0]):
+        Wt[m, n] = Wt[n, m] = v
+    vol = abs(np.linalg.det(cell))
+    return -Wt / vol * EV_A3_TO_GPA, out
+
+
+def _relax(pos, cell, x):
+    from scipy.optimize import minimize
+
+    def fun(flat):
+        out = T.evaluate(flat.reshape(-1, 3), cell, x, R1, R2)
+        return float(out["E"][0]), -out["F"].ravel()
+
+    res = minimize(fun, pos.ravel(), jac=True, method="BFGS", options={"gtol": 1e-11})
+    return res.x.reshape(-1, 3)
+
+
+def test_elastic_constants_match_table3(golden):
+    """Table 3, mini-Tersoff row: C11 = 148, C12 = 65, C44 = 75 GPa (0 K stress-strain,
+    C44 with internal relaxation of the two fcc sublattices)."""
+    x = table2(golden)
+    a0, _ = _equilibrium(x)
+    pos0, cell0 = W.diamond(1, 1, 1, a0)
+    d = 1e-4
+    s = []
+    for sign in (+1, -1):
+        F = np.eye(3)
+        F[0, 0] += sign * d
+        s.append(_stress(pos0 @ F.T, cell0 @ F.T, x)[0])
+    C11 = (s[0][0, 0] - s[1][0, 0]) / (2 * d)
+    C12 = (s[0][1, 1] - s[1][1, 1]) / (2 * d)
+    g = 1e-3
+    s44 = []
+    for sign in (+1, -1):
+        F = np.eye(3)
+        F[1, 2] = F[2, 1] = sign * g / 2
+        cell = cell0 @ F.T
+        pos = _relax(pos0 @ F.T, cell, x)
+        stress, out = _stress(pos, cell, x)
+        assert np.abs(out["F"]).max() < 1e-6
+        s44.append(stress[1, 2])
+    C44 = (s44[0] - s44[1]) / (2 * g)
+    ec = golden["elastic_constants"]
+    assert abs(C11 - ec["C11_GPa"]) <= 1.0, C11
+    assert abs(C12 - ec["C12_GPa"]) <= 1.0, C12
+    assert abs(C44 - ec["C44_GPa"]) <= 1.0, C44
+    assert abs((C12 - C44) - ec["C12_minus_C44_GPa"]) <= 2.0
+
+
+# ----------------------------------------------------------------------------
+# Special cases that reduce to textbook forms
+# ----------------------------------------------------------------------------
+
+def _isolated(points, box=40.0):
+    pts = np.asarray(points, dtype=np.float64) + box / 2
+    return pts, np.eye(3) * box
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_dimer_is_morse(seed):
+    """Sec. II.B: with S = 2 the pair part is a Morse function; a dimer has
+    zeta = 0 so b = 1 and U = f_C(r) D0 [e^{-2a(r-r0)} - 2 e^{-a(r-r0)}]."""
+    x = W.draw_params(rng(100 + seed), 1)[0]
+    D0, alpha, r0 = x[:3]
+    for r in [2.0, 2.3, r0, 2.79, 2.9, 3.1, 3.25]:
+        pos, cell = _isolated([[0, 0, 0], [r, 0, 0]])
+        e = energy(pos, cell, x)
+        morse = D0 * (math.exp(-2 * alpha * (r - r0)) - 2 * math.exp(-alpha * (r - r0)))
+        fc = 1.0 if r <= R1 else (0.0 if r >= R2 else
+                                  0.5 * (1 + math.cos(math.pi * (r - R1) / (R2 - R1))))
+        assert abs(e - fc * morse) <= 1e-13 * max(1.0, abs(morse))
+    pos, cell = _isolated([[0, 0, 0], [r0, 0, 0]])
+    out = T.evaluate(pos, cell, x, R1, R2)
+    assert abs(out["E"][0] + D0) < 1e-13 * D0
+    assert np.abs(out["F"]).max() < 1e-12
+
+
+def test_equilateral_trimer_closed_form():
+    """Each bond sees one other neighbour at 60 degrees: zeta = beta (1/2 - h)^2,
+    E = 3 D0 [x^2 - 2 b x] with x = e^{-alpha (s - r0)}."""
+    for x in [W.TABLE2_X] + list(W.draw_params(rng(7), 3)):
+        D0, alpha, r0, beta, n, h = x
+        for s in (2.3, 2.5):
+            pts = [[0, 0, 0], [s, 0, 0], [s / 2, s * math.sqrt(3) / 2, 0]]
+            pos, cell = _isolated(pts)
+            zeta = beta * (0.5 - h) ** 2
+            b = (1 + zeta ** n) ** (-1 / (2 * n))
+            e1 = math.exp(-alpha * (s - r0))
+            ref = 3 * D0 * (e1 * e1 - 2 * b * e1)
+            scale = 3 * D0 * (e1 * e1 + 2 * b * e1)      # size of the cancelling terms
+            assert abs(energy(pos, cell, x) - ref) <= 1e-13 * scale
+    x = W.TABLE2_X
+    pos, cell = _isolated([[0, 0, 0], [2.3, 0, 0], [1.15, 2.3 * math.sqrt(3) / 2, 0]])
+    assert abs(energy(pos, cell, x) - (-4.208640959670)) < 1e-11
+
+
+def test_beta_zero_reduces_to_pair_potential():
+    """beta = 0 gives g = 0, zeta = 0, b = 1: a Morse pair potential with the
+    cosine cutoff, summed here by a plain double loop over atom pairs."""
+    pos, cell = W.random_packing(rng(5), 40)
+    x = np.array(W.draw_params(rng(6), 1)[0])
+    x[3] = 0.0
+    D0, alpha, r0 = x[:3]
+    # brute-force double loop with explicit periodic images
+    L = cell[0, 0]
+    e = 0.0
+    for i in range(len(pos)):
+        for j in range(len(pos)):
+            for n1 in (-1, 0, 1):
+                for n2 in (-1, 0, 1):
+                    for n3 in (-1, 0, 1):
+                        if i == j and n1 == n2 == n3 == 0:
+                            continue
+                        dv = pos[j] + L * np.array([n1, n2, n3]) - pos[i]
+                        r = math.sqrt(float(dv @ dv))
+                        if r >= R2:
+                            continue
+                        fc = 1.0 if r <= R1 else 0.5 * (1 + math.cos(math.pi * (r - R1) / (R2 - R1)))
+                        e += 0.5 * fc * D0 * (math.exp(-2 * alpha * (r - r0))
+                                              - 2 * math.exp(-alpha * (r - r0)))
+    got = energy(pos, cell, x)
+    assert abs(got - e) <= 1e-12 * abs(e)
+
+
+def test_paper_and_morse_forms_of_pair_terms_agree():
+    """A e^{-lambda r} = D0 e^{-2 alpha (r - r0)}, B e^{-mu r} = 2 D0 e^{-alpha (r - r0)}."""
+    for x in W.draw_params(rng(9), 50):
+        A, B, lam, mu = (float(v) for v in T.derived_params(torch.tensor(x)))
+        D0, alpha, r0 = x[:3]
+        for r in np.linspace(1.9, 3.2, 14):
+            fr = A * math.exp(-lam * r)
+            fa = B * math.exp(-mu * r)
+            assert abs(fr - D0 * math.exp(-2 * alpha * (r - r0))) <= 1e-13 * fr
+            assert abs(fa - 2 * D0 * math.exp(-alpha * (r - r0))) <= 1e-13 * fa
+
+
+def test_cutoff_is_continuous_with_zero_slope_at_both_ends():
+    r = torch.tensor([R1 - 1e-9, R1, R1 + 1e-9, R2 - 1e-9, R2, R2 + 1e-9], dtype=torch.float64,
+                     requires_grad=True)
+    fc = T.cutoff(r, R1, R2)
+    (g,) = torch.autograd.grad(fc.sum(), r)
+    assert np.allclose(fc.detach().numpy(), [1, 1, 1, 0, 0, 0], atol=1e-12)
+    assert np.abs(g.numpy()).max() < 1e-7      # slope grows linearly away from R1, R2
+
+
+# ----------------------------------------------------------------------------
+# Derivatives against finite differences
+# ----------------------------------------------------------------------------
+
+def _switching_structure():
+    pos, cell = W.random_packing(rng(21), 24)
+    i, j, sh = neighbor_list(pos, cell, R2)
+    d = pos[j] + sh @ cell - pos[i]
+    r = np.linalg.norm(d, axis=1)
+    assert np.any((r > R1) & (r < R2)), "structure must exercise the switching zone"
+    return pos, cell
+
+
+def test_forces_are_minus_energy_gradient():
+    pos, cell = _switching_structure()
+    x = W.draw_params(rng(22), 1)[0]
+    out = T.evaluate(pos, cell, x, R1, R2)
+    h = 1e-5
+    fd = np.zeros_like(pos)
+    for a in range(pos.shape[0]):
+        for k in range(3):
+            p1 = pos.copy(); p1[a, k] += h
+            p2 = pos.copy(); p2[a, k] -= h
+            fd[a, k] = -(energy(p1, cell, x) - energy(p2, cell, x)) / (2 * h)
+    scale = np.abs(out["F"]).max()
+    assert np.abs(out["F"] - fd).max() <= 1e-7 * scale
+
+
+def test_virial_is_minus_strain_derivative():
+    pos, cell = _switching_structure()
+    x = W.draw_params(rng(23), 1)[0]
+    out = T.evaluate(pos, cell, x, R1, R2)
+    h = 1e-6
+    for comp, (m, n) in enumerate(T.VIRIAL6):
+        e = []
+        for sgn in (+1, -1):
+            F = np.eye(3)
+            F[m, n] += sgn * h
+            e.append(energy(pos @ F.T, cell @ F.T, x))
+        fd = -(e[0] - e[1]) / (2 * h)
+        assert abs(out["W6"][0, comp] - fd) <= 1e-7 * np.abs(out["W6"]).max()
+
+
+# ----------------------------------------------------------------------------
+# Invariances
+# ----------------------------------------------------------------------------
+
+def _random_rotation(seed):
+    q, r = np.linalg.qr(rng(seed).normal(size=(3, 3)))
+    q = q @ np.diag(np.sign(np.diag(r)))
+    if np.linalg.det(q) < 0:
+        q[:, 0] *= -1
+    return q
+
+
+def test_invariances():
+    ws = W.strained_diamond_cells(31, 1)[0]
+    pos, cell = ws
+    x = W.draw_params(rng(32), 1)[0]
+    base = T.evaluate(pos, cell, x, R1, R2)
+    E0, F0 = base["E"][0], base["F"]
+    sF = np.abs(F0).max()
+    assert np.abs(F0.sum(axis=0)).max() <= 1e-12 * sF * len(pos)
+    # rotation of positions and cell
+    Rm = _random_rotation(33)
+    rot = T.evaluate(pos @ Rm.T, cell @ Rm.T, x, R1, R2)
+    assert abs(rot["E"][0] - E0) <= 1e-12 * abs(E0)
+    assert np.abs(rot["F"] - F0 @ Rm.T).max() <= 1e-11 * sF
+    # translation
+    tr = T.evaluate(pos + np.array([0.37, -1.2, 4.4]), cell, x, R1, R2)
+    assert abs(tr["E"][0] - E0) <= 1e-12 * abs(E0)
+    assert np.abs(tr["F"] - F0).max() <= 1e-11 * sF
+    # permutation of atom labels
+    perm = rng(34).permutation(len(pos))
+    pe = T.evaluate(pos[perm], cell, x, R1, R2)
+    assert abs(pe["E"][0] - E0) <= 1e-12 * abs(E0)
+    assert np.abs(pe["F"] - F0[perm]).max() <= 1e-12 * sF
+    # 2x1x1 supercell doubles the energy and repeats the forces
+    pos2 = np.concatenate([pos, pos + cell[0]])
+    cell2 = cell.copy(); cell2[0] *= 2
+    sc = T.evaluate(pos2, cell2, x, R1, R2)
+    assert abs(sc["E"][0] - 2 * E0) <= 1e-12 * abs(E0)
+    assert np.abs(sc["F"] - np.concatenate([F0, F0])).max() <= 1e-11 * sF
+    assert np.allclose(sc["W6"][0], 2 * base["W6"][0], rtol=1e-11, atol=1e-11)
+
+
+# ----------------------------------------------------------------------------
+# Neighbour enumeration
+# ----------------------------------------------------------------------------
+
+def _tiny_cells():
+    out = []
+    pos, cell = W.diamond(1, 1, 1)                       # 8 atoms, L < 2 R2
+    out.append((W.displace(rng(41), pos, 0.1), cell))
+    F = np.eye(3); F[0, 1] = 0.3; F[2, 0] = -0.2         # strongly sheared
+    out.append(((pos @ F.T), cell @ F.T))
+    # 2-atom cell with a lattice vector shorter than R2: self-image neighbours
+    cell = np.array([[2.5, 0, 0], [0.4, 3.9, 0], [0.3, 0.2, 4.1]])
+    out.append((np.array([[0.1, 0.2, 0.3], [1.3, 1.9, 2.2]]), cell))
+    pos, cell = W.random_packing(rng(42), 10)
+    out.append((pos, cell))
+    return out
+
+
+def test_neighbor_enumeration_matches_naive_loop():
+    for pos, cell in _tiny_cells():
+        i, j, s = neighbor_list(pos, cell, R2)
+        got = sorted(zip(i.tolist(), j.tolist(), *s.T.tolist()))
+        ref = neighbor_list_naive(pos.tolist(), cell.tolist(), R2, nmax=3)
+        assert got == ref
+        assert len(got) > 0
+
+
+def test_neighbor_list_is_symmetric():
+    for pos, cell in _tiny_cells():
+        i, j, s = neighbor_list(pos, cell, R2)
+        fwd = set(zip(i.tolist(), j.tolist(), *s.T.tolist()))
+        rev = set(zip(j.tolist(), i.tolist(), *(-s).T.tolist()))
+        assert fwd == rev
+
+
+def test_coincident_atoms_are_an_error():
+    pos = np.array([[1.0, 1.0, 1.0], [1.0, 1.0, 1.0], [2.5, 1, 1]])
+    with pytest.raises(ValueError):
+        neighbor_list(pos, np.eye(3) * 10, R2)
+
+
+# ----------------------------------------------------------------------------
+# Per-atom virial and heat current
+# ----------------------------------------------------------------------------
+
+def test_per_atom_virial_sums_to_virial():
+    pos, cell = _switching_structure()
+    x = W.draw_params(rng(51), 1)[0]
+    out = T.evaluate(pos, cell, x, R1, R2, atom_virial=True)
+    tot = out["Wi"].sum(axis=0)
+    for comp, (m, n) in enumerate(T.VIRIAL6):
+        assert abs(tot[m, n] - out["W6"][0, comp]) <= 1e-12 * np.abs(out["W6"]).max()
+        assert abs(tot[n, m] - out["W6"][0, comp]) <= 1e-12 * np.abs(out["W6"]).max()
+
+
+def test_per_atom_virial_energy_moment_identity():
+    """For an isolated cluster, sum_i W_i v_i = sum_i r_i dU_i/dt + sum_i r_i (F_i . v_i),
+    the time derivative of the energy moment minus the kinetic-free terms.  With
+    only atom m moving at unit speed along axis k the left side is column k of
+    W_m, and the right side needs only site energies and forces."""
+    pts, _ = W.random_packing(rng(61), 20)
+    pos, cell = _isolated(pts - pts.mean(axis=0), box=60.0)
+    x = W.draw_params(rng(62), 1)[0]
+    out = T.evaluate(pos, cell, x, R1, R2, atom_virial=True)
+    h = 1e-6
+    for m in (0, 7):
+        for k in range(3):
+            up = pos.copy(); up[m, k] += h
+            dn = pos.copy(); dn[m, k] -= h
+            dU = (T.evaluate(up, cell, x, R1, R2)["U"] - T.evaluate(dn, cell, x, R1, R2)["U"]) / (2 * h)
+            rhs = (pos * dU[:, None]).sum(axis=0) + pos[m] * out["F"][m, k]
+            assert np.allclose(out["Wi"][m][:, k], rhs, atol=1e-7 * np.abs(out["Wi"]).max())
+
+
+def test_local_cluster_matches_full_evaluation():
+    pos, cell = W.diamond(4, 4, 4)
+    pos = W.displace(rng(71), pos, 0.1)
+    x = W.draw_params(rng(72), 1)[0]
+    full = T.evaluate(pos, cell, x, R1, R2, atom_virial=True)
+    atoms = [0, 17, 300, 511]
+    loc = T.local_forces(pos, cell, x, atoms, R1, R2)
+    s = np.abs(full["F"]).max()
+    assert np.abs(loc["F"] - full["F"][atoms]).max() <= 1e-12 * s
+    assert np.abs(loc["U"] - full["U"][atoms]).max() <= 1e-12
+    assert np.abs(loc["Wi"] - full["Wi"][atoms]).max() <= 1e-12 * np.abs(full["Wi"]).max()
+
+
+# ----------------------------------------------------------------------------
+# Fitness and its gradient
+# ----------------------------------------------------------------------------
+
+def _small_training_set():
+    structs = W.strained_diamond_cells(81, 2, reps=(1, 1, 2))
+    structs.append(W.random_packing(rng(82), 12))
+    return W.make_set(structs)
+
+
+def test_fitness_vanishes_at_the_reference_parameters():
+    s = _small_training_set()
+    xs = W.draw_params(rng(83), 1)[0]
+    refs = T.reference_data(s, xs, R1, R2)
+    Z = T.fitness(s, xs, refs)[0]
+    assert np.all(Z == 0.0)
+    Z2 = T.fitness(s, W.draw_params(rng(84), 1), refs)[0]
+    assert np.all(Z2[1:] > 0) and abs(Z2[0] - Z2[1:].sum()) < 1e-15 * Z2[0]
+
+
+def test_fitness_definition_by_hand():
+    """Z terms are relative RMSEs over structures / virial components / atoms."""
+    s = _small_training_set()
+    refs = T.reference_data(s, W.draw_params(rng(85), 1)[0], R1, R2)
+    x = W.draw_params(rng(86), 1)[0]
+    out = T.evaluate_set(s, x, R1, R2)
+    n = s.sizes().astype(float)
+    e = out["E"] / n
+    w = out["W6"] / n[:, None]
+    Ze = math.sqrt(sum((e - refs["e"]) ** 2) / sum(refs["e"] ** 2))
+    Zv = math.sqrt(float(((w - refs["w"]) ** 2).sum() / (refs["w"] ** 2).sum()))
+    Zf = math.sqrt(float(((out["F"] - refs["f"]) ** 2).sum() / (refs["f"] ** 2).sum()))
+    Z = T.fitness(s, x, refs, weights=(0.5, 2.0, 1.5))[0]
+    assert np.allclose(Z, [0.5 * Ze + 2.0 * Zv + 1.5 * Zf, Ze, Zv, Zf], rtol=1e-13)
+
+
+def test_fitness_gradient_matches_central_differences():
+    s = _small_training_set()
+    refs = T.reference_data(s, W.draw_params(rng(87), 1)[0], R1, R2)
+    top = T.topology(s, R2)
+    for x in W.draw_params(rng(88), 2):
+        Z, G = T.fitness_grad(s, x, refs, weights=(1.0, 0.7, 1.3), topology=top)
+        fd = np.zeros(6)
+        for k in range(6):
+            h = 1e-6 * max(1.0, abs(x[k]))
+            xp = x.copy(); xp[k] += h
+            xm = x.copy(); xm[k] -= h
+            zp = T.fitness(s, xp, refs, weights=(1.0, 0.7, 1.3), topology=top)[0, 0]
+            zm = T.fitness(s, xm, refs, weights=(1.0, 0.7, 1.3), topology=top)[0, 0]
+            fd[k] = (zp - zm) / (2 * h)
+        assert np.abs(G[0] - fd).max() <= 1e-6 * np.abs(G[0]).max()
+
+
+def test_energy_gradient_closed_form_for_diamond():
+    """dE/dD0 = E/D0 exactly (the energy is linear in D0), and d e/d beta from the
+    closed form, checked through the fitness gradient of a one-structure set."""
+    a = 5.43
+    pos, cell = W.diamond(1, 1, 1, a)
+    s = W.make_set([(pos, cell)])
+    x = np.array(W.TABLE2_X)
+    e = T.diamond_closed_form(x, a)
+    refs = {"e": np.array([e - 0.1]), "w": np.ones((1, 6)), "f": np.ones((8, 3))}
+    Z, G = T.fitness_grad(s, x, refs, weights=(1.0, 0.0, 0.0))
+    # Z_e = |e - e*| / |e*|  ->  dZ_e/dx = sign(e - e*) de/dx / |e*|
+    de_dD0 = G[0, 0] * abs(refs["e"][0])
+    assert abs(de_dD0 - e / x[0]) <= 1e-12 * abs(e / x[0])
+    hb = 1e-6
+    xp = x.copy(); xp[3] += hb
+    xm = x.copy(); xm[3] -= hb
+    de_db = (T.diamond_closed_form(xp, a) - T.diamond_closed_form(xm, a)) / (2 * hb)
+    assert abs(G[0, 3] * abs(refs["e"][0]) - de_db) <= 1e-7 * abs(de_db)

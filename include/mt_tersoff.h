@@ -1,0 +1,198 @@
+/*
+ * mt_tersoff.h -- C ABI of the MI355X minimal-Tersoff fitting library.
+ *
+ * The library evaluates the minimal Tersoff potential of Fan et al.,
+ * "A minimal Tersoff potential for diamond silicon with improved descriptions
+ * of elastic and phonon transport properties" (arXiv:1909.11474), for every
+ * candidate parameter set of a genetic-algorithm population and every training
+ * structure, and returns energies, forces and virials (Sec. II) or the weighted
+ * relative-RMSE fitness Z = w_e Z_e + w_v Z_v + w_f Z_f (Sec. III.B) and its
+ * gradient with respect to the six parameters.  One GPU kernel covers all
+ * candidate x structure pairs of a call, as the GPU implementation of
+ * Sec. III.C describes.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units: energies eV, lengths Angstrom, forces eV/A, velocities A/fs.
+ * Parameters: x[p*6 + k], k = 0..5 = D0 (eV), alpha (1/A), r0 (A), beta, n, h
+ *   (Sec. II.B; the Pauling slope S is fixed to 2, so A = D0 exp(2 alpha r0),
+ *   B = 2 D0 exp(alpha r0), lambda = 2 alpha, mu = alpha).  x lives in device
+ *   memory, float64, row-major [P][6].
+ * Virial: W = -dE/d(strain), positive under compression; six components in
+ *   the order xx, yy, zz, yz, zx, xy.  Per-atom virial W_i (9 components,
+ *   row-major xx xy xz yx yy yz zx zy zz) is sum_j r_ij (x) dU_j/dr_ji with
+ *   r_ij = r_j - r_i, and sums over atoms to W.
+ * Memory: every pointer argument marked "device" is device memory owned by the
+ *   caller (for instance a torch tensor's data_ptr()); the library never keeps
+ *   a caller pointer beyond the call.  Arrays are contiguous and float64
+ *   unless stated otherwise.
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *   Evaluation calls are enqueued on it and return without synchronising;
+ *   set creation and reference attachment synchronise it.
+ * Errors: every call returns MT_OK (0) or a negative mt_status; mt_last_error()
+ *   then gives a message for the calling thread.  Argument errors are detected
+ *   before any work is enqueued.  A candidate whose parameters are outside the
+ *   potential's domain (non-finite, D0 <= 0, alpha <= 0, n <= 0, beta < 0) is
+ *   not a call error: its outputs are NaN and the other candidates are
+ *   unaffected.
+ * Threads: an mt_set may be used from one thread at a time.
+ */
+#ifndef MT_TERSOFF_H
+#define MT_TERSOFF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mt_set mt_set;   /* opaque: structures, neighbour lists, references */
+
+enum mt_status {
+    MT_OK = 0,
+    MT_EINVAL = -1,          /* bad argument (NULL, size <= 0, R2 <= R1, ...)         */
+    MT_ENOMEM = -2,          /* device allocation failed                            */
+    MT_EHIP = -3,            /* a HIP runtime call failed                           */
+    MT_ENBR_OVERFLOW = -4,   /* an atom has more neighbours than the capacity       */
+    MT_ENOREF = -5,          /* fitness requested but no reference data attached    */
+    MT_ESTATE = -6,          /* call not valid in the set's current state           */
+    MT_ECOINCIDENT = -7      /* two atoms (or an atom and an image) coincide        */
+};
+
+enum mt_precision {
+    MT_FP64 = 0,             /* all arithmetic in float64                            */
+    MT_FP32_ACC64 = 1        /* per-pair/triplet arithmetic in float32; per-structure
+                                energy, virial and fitness sums in float64           */
+};
+
+enum mt_schedule {
+    MT_BATCHED = 0,          /* one launch covers all candidate x structure pairs
+                                (replayed from a captured HIP graph)                 */
+    MT_PLAIN = 1             /* one launch per (candidate, structure) pair           */
+};
+
+/* Largest coordination number handled by the batched kernels. */
+#define MT_MAX_NBR 16
+/* Largest structure handled by the batched kernels; bigger structures take the
+ * two-pass large-system kernels. */
+#define MT_MAX_BATCHED_ATOMS 512
+
+/*
+ * Build a structure set: copies the structures and finds, on the GPU with a
+ * cell list, every neighbour entry (j, periodic image T) of every atom i with
+ * 0 < |r_j + T - r_i| < R2.  The cutoff f_C of Sec. II.A vanishes at and
+ * beyond R2, so these are exactly the interacting pairs; R1 and R2 are fixed by
+ * hand in the paper (Sec. II.B: 2.8 and 3.2 A), not fitted, so the neighbour
+ * lists and all pair geometry are built once here and reused by every call.
+ * Cells may be triclinic and smaller than 2 R2 (several images of one atom,
+ * or of the atom itself, can then be neighbours).
+ *
+ *   out          receives the new set (host pointer to a host pointer)
+ *   n_struct     S >= 1
+ *   atom_offset  host int64 [S+1]; atoms of structure s are
+ *                atom_offset[s] .. atom_offset[s+1]-1; atom_offset[0] = 0 and
+ *                every structure has at least one atom
+ *   pos          device float64 [3][N_tot] Cartesian positions, SoA (x row,
+ *                then y row, then z row); atoms need not be wrapped into the cell
+ *   cell         device float64 [S][3][3]; rows are the lattice vectors a, b, c
+ *   R1, R2       cutoff radii, 0 < R1 < R2
+ *   max_nbr      neighbour capacity per atom, 1..MT_MAX_NBR
+ * Returns MT_ENBR_OVERFLOW if any atom has more than max_nbr neighbours and
+ * MT_ECOINCIDENT for coincident atoms; no set is created then.
+ */
+int mt_set_create(mt_set** out, int n_struct, const int64_t* atom_offset,
+                  const double* pos, const double* cell, double R1, double R2,
+                  int max_nbr, void* stream);
+
+/*
+ * Attach reference data for the fitness (Sec. III.B), copied into the set:
+ *   e_ref  device [S]       reference energy per atom of each structure (eV/atom)
+ *   w_ref  device [S][6]    reference virial per atom (eV/atom), xx yy zz yz zx xy
+ *   f_ref  device [3][N_tot] reference forces (eV/A), SoA
+ * Each of sum e_ref^2, sum w_ref^2 and sum |f_ref|^2 must be positive (they are
+ * the denominators of the relative RMSEs); otherwise MT_EINVAL.
+ */
+int mt_set_attach_reference(mt_set* set, const double* e_ref, const double* w_ref,
+                            const double* f_ref, void* stream);
+
+/* Release the set and its device memory.  NULL is accepted. */
+int mt_set_destroy(mt_set* set);
+
+/*
+ * Sizes of a set, written to host int64 stats[8]:
+ *   0 n_struct, 1 n_atoms, 2 n_bonds (directed neighbour entries),
+ *   3 n_triplets (ordered (j, k != j) pairs of entries sharing a centre atom),
+ *   4 largest coordination, 5 largest structure (atoms),
+ *   6 structures handled by the batched kernels, 7 by the large-system kernels.
+ */
+int mt_set_stats(const mt_set* set, int64_t* stats);
+
+/*
+ * Copy the neighbour entries out, in the caller's atom numbering, for checks:
+ *   i, j    device int32 [n_bonds]  global atom indices (centre, neighbour)
+ *   shift   device int32 [3][n_bonds] lattice-vector multiples n1 n2 n3 of the
+ *           image: r_ij = r_j + n1 a + n2 b + n3 c - r_i
+ * Entries are grouped by centre atom; the order inside a group is unspecified.
+ */
+int mt_set_neighbors(const mt_set* set, int32_t* i, int32_t* j, int32_t* shift, void* stream);
+
+/*
+ * Energies, forces and virials of P parameter sets on every structure
+ * (Sec. II.A/II.B; forces F_i = -dE/dr_i and virial W = -dE/d(strain), i.e. the
+ * exact derivatives of the site-energy sum, which the cited force and virial
+ * formulas compute).  Any output may be NULL to skip it.
+ *   x             device [P][6]
+ *   energy        device [P][S]        total energy of each structure (eV)
+ *   force         device [P][3][N_tot] forces (eV/A)
+ *   virial        device [P][S][6]     total virial of each structure (eV)
+ *   atom_virial   device [P][9][N_tot] per-atom virial (eV)
+ *   vel           device [3][N_tot]    velocities (A/fs), needed for heat_current
+ *   heat_current  device [P][3]        sum_i W_i v_i over all atoms (eV A/fs)
+ */
+int tersoff_eval(mt_set* set, const double* x, int P, int precision, int schedule,
+                 double* energy, double* force, double* virial, double* atom_virial,
+                 const double* vel, double* heat_current, void* stream);
+
+/*
+ * Fitness of P parameter sets against the attached reference (Sec. III.B):
+ *   Z_e = sqrt(sum_s (e_s - e*_s)^2 / sum_s e*_s^2), e_s = E_s / N_s,
+ *   Z_v the same over the six virial-per-atom components of every structure,
+ *   Z_f the same over all force components, Z = w_e Z_e + w_v Z_v + w_f Z_f.
+ *   w   host float64 [3] = w_e, w_v, w_f
+ *   Z   device [P][4] = Z, Z_e, Z_v, Z_f
+ * MT_ENOREF without a reference.
+ */
+int fitness_eval(mt_set* set, const double* x, int P, const double* w, int precision,
+                 int schedule, double* Z, void* stream);
+
+/*
+ * Fitness and its gradient dZ/dx with respect to the six parameters (the
+ * derivative of the Sec. III.B fitness, including the force and virial terms,
+ * which need mixed second derivatives of the energy).  A term with Z_x = 0
+ * contributes no gradient.
+ *   Z     device [P][4]
+ *   dZdx  device [P][6]
+ */
+int fitness_grad(mt_set* set, const double* x, int P, const double* w, int precision,
+                 double* Z, double* dZdx, void* stream);
+
+/*
+ * Choose launch shapes (block size, candidate tile, schedule) for this set
+ * and population size by timing the candidates on the GPU; the choice is kept
+ * in the set and used by later calls with the same P and precision.  When
+ * cache_path is not NULL the choice is also appended to that text file, and a
+ * matching entry already there is used without timing.
+ */
+int mt_autotune(mt_set* set, int P, int precision, const char* cache_path);
+
+/* Message for the calling thread's most recent error (never NULL). */
+const char* mt_last_error(void);
+
+/* Library version string. */
+const char* mt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MT_TERSOFF_H */

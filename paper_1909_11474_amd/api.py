@@ -1,0 +1,238 @@
+"""Python binding of the C ABI (include/mt_tersoff.h).
+
+Only argument marshalling happens here: tensors are moved to the GPU in the
+layouts the ABI documents and their data pointers are handed to the library,
+together with the current HIP stream.  Every computation runs in the HIP
+kernels of libmt_tersoff.so.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_PREC = {"fp64": L.MT_FP64, "fp32": L.MT_FP32_ACC64, L.MT_FP64: L.MT_FP64,
+         L.MT_FP32_ACC64: L.MT_FP32_ACC64}
+_SCHED = {"batched": L.MT_BATCHED, "plain": L.MT_PLAIN, L.MT_BATCHED: L.MT_BATCHED,
+          L.MT_PLAIN: L.MT_PLAIN}
+
+
+def _prec(p) -> int:
+    try:
+        return _PREC[p]
+    except KeyError:
+        raise ValueError(f"precision must be 'fp32' or 'fp64', got {p!r}") from None
+
+
+def _sched(s) -> int:
+    try:
+        return _SCHED[s]
+    except KeyError:
+        raise ValueError(f"schedule must be 'batched' or 'plain', got {s!r}") from None
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class TersoffSet:
+    """A set of periodic structures on one GPU, with neighbour lists and bond
+    geometry built once, and optional reference data for the fitness.
+
+    pos     [N, 3] Cartesian positions (A), structures concatenated
+    cell    [S, 3, 3] lattice vectors as rows (A)
+    offset  [S + 1] first atom of every structure, offset[S] = N
+    """
+
+    def __init__(self, pos, cell, offset, R1: float = 2.8, R2: float = 3.2,
+                 max_nbr: int = L.MT_MAX_NBR, device=None):
+        self._lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("TersoffSet needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self._handle = ctypes.c_void_p()
+        off = np.ascontiguousarray(np.asarray(offset), dtype=np.int64)
+        self.offset = off
+        self.S = int(off.shape[0] - 1)
+        self.N = int(off[-1])
+        pos_t = torch.as_tensor(np.asarray(pos, dtype=np.float64) if not torch.is_tensor(pos) else pos)
+        cell_t = torch.as_tensor(np.asarray(cell, dtype=np.float64) if not torch.is_tensor(cell) else cell)
+        if tuple(pos_t.shape) != (self.N, 3):
+            raise ValueError(f"pos must be [{self.N}, 3], got {tuple(pos_t.shape)}")
+        if tuple(cell_t.shape) != (self.S, 3, 3):
+            raise ValueError(f"cell must be [{self.S}, 3, 3], got {tuple(cell_t.shape)}")
+        with torch.cuda.device(self.device):
+            pos_soa = pos_t.to(torch.float64).t().contiguous().to(self.device)
+            cell_d = cell_t.to(torch.float64).contiguous().to(self.device)
+            rc = self._lib.mt_set_create(ctypes.byref(self._handle), self.S,
+                                         off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                         _ptr(pos_soa), _ptr(cell_d), float(R1), float(R2),
+                                         int(max_nbr), self._stream())
+        L.check(rc, "mt_set_create")
+        self.R1, self.R2 = float(R1), float(R2)
+        self.sizes = np.diff(off)
+
+    # -- plumbing ---------------------------------------------------------------
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _x(self, x) -> torch.Tensor:
+        xt = torch.as_tensor(x) if not torch.is_tensor(x) else x
+        xt = xt.detach().to(device=self.device, dtype=torch.float64)
+        if xt.dim() == 1:
+            xt = xt[None]
+        if xt.dim() != 2 or xt.shape[1] != 6:
+            raise ValueError(f"x must be [P, 6], got {tuple(xt.shape)}")
+        return xt.contiguous()
+
+    def close(self):
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            self._lib.mt_set_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- queries ----------------------------------------------------------------
+    def stats(self) -> dict:
+        out = (ctypes.c_int64 * 8)()
+        L.check(self._lib.mt_set_stats(self._handle, out), "mt_set_stats")
+        keys = ("n_struct", "n_atoms", "n_bonds", "n_triplets", "max_coordination",
+                "max_atoms", "n_batched", "n_large")
+        return {k: int(v) for k, v in zip(keys, out)}
+
+    def neighbors(self):
+        """(i, j, shift [nb, 3]) as numpy int64 arrays, grouped by centre atom."""
+        nb = self.stats()["n_bonds"]
+        with torch.cuda.device(self.device):
+            i = torch.empty(max(nb, 1), dtype=torch.int32, device=self.device)
+            j = torch.empty(max(nb, 1), dtype=torch.int32, device=self.device)
+            sh = torch.empty(3 * max(nb, 1), dtype=torch.int32, device=self.device)
+            L.check(self._lib.mt_set_neighbors(self._handle, _ptr(i), _ptr(j), _ptr(sh),
+                                               self._stream()), "mt_set_neighbors")
+            torch.cuda.current_stream(self.device).synchronize()
+        shift = sh.view(3, -1)[:, :nb].t().cpu().numpy().astype(np.int64)
+        return i[:nb].cpu().numpy().astype(np.int64), j[:nb].cpu().numpy().astype(np.int64), shift
+
+    # -- reference data ---------------------------------------------------------
+    def attach_reference(self, e_ref, w_ref, f_ref):
+        """e_ref [S] eV/atom, w_ref [S, 6] eV/atom (xx yy zz yz zx xy), f_ref [N, 3] eV/A."""
+        def dev(a, shape):
+            t = torch.as_tensor(np.asarray(a, dtype=np.float64) if not torch.is_tensor(a) else a)
+            t = t.to(torch.float64)
+            if tuple(t.shape) != shape:
+                raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+            return t
+        e = dev(e_ref, (self.S,)).contiguous().to(self.device)
+        w = dev(w_ref, (self.S, 6)).contiguous().to(self.device)
+        f = dev(f_ref, (self.N, 3)).t().contiguous().to(self.device)
+        with torch.cuda.device(self.device):
+            L.check(self._lib.mt_set_attach_reference(self._handle, _ptr(e), _ptr(w), _ptr(f),
+                                                      self._stream()), "mt_set_attach_reference")
+
+    # -- evaluation -------------------------------------------------------------
+    def tersoff_eval(self, x, precision="fp32", schedule="batched", energy=True, forces=True,
+                     virial=True, atom_virial=False, velocities=None):
+        """Energies [P,S], forces [P,N,3], virials [P,S,6], per-atom virials [P,N,3,3]
+        and heat current [P,3] (when velocities [N,3] in A/fs are given)."""
+        xt = self._x(x)
+        P = xt.shape[0]
+        kw = dict(dtype=torch.float64, device=self.device)
+        out = {}
+        with torch.cuda.device(self.device):
+            E = torch.empty(P, self.S, **kw) if energy else None
+            F = torch.empty(P, 3, self.N, **kw) if forces else None
+            W = torch.empty(P, self.S, 6, **kw) if virial else None
+            Wi = torch.empty(P, 9, self.N, **kw) if atom_virial else None
+            vel = None
+            J = None
+            if velocities is not None:
+                v = torch.as_tensor(np.asarray(velocities, dtype=np.float64) if not torch.is_tensor(velocities) else velocities)
+                vel = v.to(torch.float64).t().contiguous().to(self.device)
+                J = torch.empty(P, 3, **kw)
+            rc = self._lib.tersoff_eval(self._handle, _ptr(xt), P, _prec(precision), _sched(schedule),
+                                        _ptr(E), _ptr(F), _ptr(W), _ptr(Wi), _ptr(vel), _ptr(J),
+                                        self._stream())
+        L.check(rc, "tersoff_eval")
+        if E is not None:
+            out["E"] = E
+        if F is not None:
+            out["F"] = F.transpose(1, 2)
+        if W is not None:
+            out["W"] = W
+        if Wi is not None:
+            out["Wi"] = Wi.view(P, 3, 3, self.N).permute(0, 3, 1, 2)
+        if J is not None:
+            out["J"] = J
+        return out
+
+    def fitness(self, x, weights=(1.0, 1.0, 1.0), precision="fp32", schedule="batched",
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """[P, 4] = Z, Z_e, Z_v, Z_f (device tensor, float64)."""
+        xt = self._x(x)
+        P = xt.shape[0]
+        w = (ctypes.c_double * 3)(*[float(v) for v in weights])
+        with torch.cuda.device(self.device):
+            Z = out if out is not None else torch.empty(P, 4, dtype=torch.float64, device=self.device)
+            rc = self._lib.fitness_eval(self._handle, _ptr(xt), P, w, _prec(precision),
+                                        _sched(schedule), _ptr(Z), self._stream())
+        L.check(rc, "fitness_eval")
+        return Z
+
+    def fitness_grad(self, x, weights=(1.0, 1.0, 1.0), precision="fp32"):
+        """(Z [P, 4], dZ/dx [P, 6]) as device tensors."""
+        xt = self._x(x)
+        P = xt.shape[0]
+        w = (ctypes.c_double * 3)(*[float(v) for v in weights])
+        with torch.cuda.device(self.device):
+            Z = torch.empty(P, 4, dtype=torch.float64, device=self.device)
+            G = torch.empty(P, 6, dtype=torch.float64, device=self.device)
+            rc = self._lib.fitness_grad(self._handle, _ptr(xt), P, w, _prec(precision), _ptr(Z),
+                                        _ptr(G), self._stream())
+        L.check(rc, "fitness_grad")
+        return Z, G
+
+    def autotune(self, P: int, precision="fp32", cache_path: Optional[str] = None):
+        with torch.cuda.device(self.device):
+            rc = self._lib.mt_autotune(self._handle, int(P), _prec(precision),
+                                       cache_path.encode() if cache_path else None)
+        L.check(rc, "mt_autotune")
+
+
+def from_structures(structs, R1: float = 2.8, R2: float = 3.2, max_nbr: int = L.MT_MAX_NBR,
+                    device=None) -> TersoffSet:
+    """Build a TersoffSet from an object with .pos [N,3], .cell [S,3,3], .offset [S+1]."""
+    return TersoffSet(structs.pos, structs.cell, structs.offset, R1, R2, max_nbr, device)
+
+
+class TersoffFitness(torch.autograd.Function):
+    """Z(x) for a population x [P, 6] as a differentiable function.
+
+    forward: fitness_eval, or fitness_grad when x requires a gradient;
+    backward: grad_Z[:, None] * dZ/dx."""
+
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, tset: TersoffSet, weights: Sequence[float] = (1.0, 1.0, 1.0),
+                precision: str = "fp32"):
+        if ctx.needs_input_grad[0]:
+            Z, G = tset.fitness_grad(x, weights, precision)
+            ctx.save_for_backward(G.to(x.dtype).to(x.device))
+        else:
+            Z = tset.fitness(x, weights, precision)
+        return Z[:, 0].to(x.device)
+
+    @staticmethod
+    def backward(ctx, grad_z: torch.Tensor):
+        (G,) = ctx.saved_tensors
+        return grad_z[:, None] * G, None, None, None
+
+
+def tersoff_fitness(x: torch.Tensor, tset: TersoffSet, weights=(1.0, 1.0, 1.0), precision="fp32"):
+    return TersoffFitness.apply(x, tset, tuple(weights), precision)

@@ -1,0 +1,382 @@
+// C ABI entry points (declared in include/mt_tersoff.h): argument checks, set
+// lifecycle, dispatch to the batched / plain / large-structure kernels, HIP
+// graph replay of the batched fitness path, and the launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "mt_host.h"
+#include "mt_tersoff.h"
+
+namespace mt {
+
+static thread_local std::string g_last_error = "no error";
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string("HIP error '") + hipGetErrorString(e) + "' in " + what;
+    return e == hipErrorOutOfMemory ? MT_ENOMEM : MT_EHIP;
+}
+
+}  // namespace mt
+
+using namespace mt;
+
+#define HIPCHECK(call)                                   \
+    do {                                                 \
+        hipError_t _e = (call);                          \
+        if (_e != hipSuccess) return hip_fail(_e, #call); \
+    } while (0)
+
+#define TRY(call)                 \
+    do {                          \
+        int _rc = (call);         \
+        if (_rc != MT_OK) return _rc; \
+    } while (0)
+
+static int fail(int code, const std::string& msg) {
+    set_error(msg);
+    return code;
+}
+
+mt::SetDev mt_set::dev() const {
+    SetDev d{};
+    d.S = S; d.N = N; d.kcap = kcap; d.nb = nb; d.nslots = nslots;
+    d.st_off = st_off.as<int>(); d.st_boff = st_boff.as<int>(); d.st_npad = st_npad.as<int>();
+    d.st_kmax = st_kmax.as<int>(); d.st_slot = st_slot.as<int>();
+    d.perm = perm.as<int>(); d.nnb = nnb.as<int>(); d.lbo = lbo.as<int>();
+    d.rev = rev.as<int>(); d.jl = jl.as<int>();
+    const size_t KN = (size_t)kcap * N;
+    const float* f = gf.as<float>();
+    d.gf = GeomArrays<float>{f, f + KN, f + 2 * KN, f + 3 * KN, gf_rlo.as<float>(), f + 4 * KN,
+                             f + 5 * KN, f + 6 * KN};
+    const double* g = gd.as<double>();
+    d.gd = GeomArrays<double>{g, g + KN, g + 2 * KN, g + 3 * KN, nullptr, g + 4 * KN,
+                              g + 5 * KN, g + 6 * KN};
+    d.fref32 = fref32.as<float>();
+    d.fref64 = fref64.as<double>();
+    return d;
+}
+
+static void clear_graphs(mt_set* set) {
+    for (auto& kv : set->graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    set->graphs.clear();
+}
+
+mt_set::~mt_set() {
+    clear_graphs(this);
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+}
+
+// Reserve per-call workspaces; any reallocation invalidates captured graphs.
+static int ensure_workspace(mt_set* set, int P, int nv) {
+    const void* before[2] = {set->params_d.p, set->partial.p};
+    HIPCHECK(set->params_f.reserve(sizeof(float) * kNParam * (size_t)P));
+    HIPCHECK(set->params_d.reserve(sizeof(double) * kNParam * (size_t)P));
+    HIPCHECK(set->partial.reserve(sizeof(double) * nv * (size_t)P * std::max(1, set->nslots)));
+    if (before[0] != set->params_d.p || before[1] != set->partial.p) clear_graphs(set);
+    return MT_OK;
+}
+
+static int check_common(mt_set* set, const double* x, int P, int precision) {
+    if (!set) return fail(MT_EINVAL, "set is NULL");
+    if (!x) return fail(MT_EINVAL, "x is NULL");
+    if (P <= 0) return fail(MT_EINVAL, "P must be positive");
+    if (precision != MT_FP64 && precision != MT_FP32_ACC64)
+        return fail(MT_EINVAL, "precision must be MT_FP64 or MT_FP32_ACC64");
+    if ((long long)P * std::max(1, set->nslots) * kNVEval > (1ll << 31))
+        return fail(MT_EINVAL, "P too large for this set");
+    return MT_OK;
+}
+
+static LaunchCfg cfg_for(mt_set* set, int P, int precision) {
+    auto it = set->tuned.find({P, precision});
+    if (it != set->tuned.end()) return it->second;
+    return default_cfg(set, P, precision);
+}
+
+extern "C" {
+
+const char* mt_last_error(void) { return g_last_error.c_str(); }
+
+const char* mt_version(void) { return "mt_tersoff 0.1 (gfx950)"; }
+
+int mt_set_create(mt_set** out, int n_struct, const int64_t* atom_offset, const double* pos,
+                  const double* cell, double R1, double R2, int max_nbr, void* stream) {
+    if (!out) return fail(MT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_struct <= 0) return fail(MT_EINVAL, "n_struct must be positive");
+    if (!atom_offset || !pos || !cell) return fail(MT_EINVAL, "atom_offset, pos and cell must not be NULL");
+    if (!(R1 > 0.0) || !(R2 > R1) || !std::isfinite(R2))
+        return fail(MT_EINVAL, "cutoffs must satisfy 0 < R1 < R2 < inf");
+    if (max_nbr < 1 || max_nbr > MT_MAX_NBR)
+        return fail(MT_EINVAL, "max_nbr must be in 1.." + std::to_string(MT_MAX_NBR));
+    if (atom_offset[0] != 0) return fail(MT_EINVAL, "atom_offset[0] must be 0");
+    for (int s = 0; s < n_struct; ++s)
+        if (atom_offset[s + 1] <= atom_offset[s])
+            return fail(MT_EINVAL, "structure " + std::to_string(s) + " has no atoms");
+    const long long N = atom_offset[n_struct];
+    if (N * (long long)max_nbr >= (1ll << 31)) return fail(MT_EINVAL, "too many atoms");
+    auto set = new mt_set();
+    set->S = n_struct;
+    set->N = (int)N;
+    set->kcap = max_nbr;
+    set->R1 = R1;
+    set->R2 = R2;
+    (void)hipGetDevice(&set->device);
+    int rc = build_set(set, atom_offset, pos, cell, (hipStream_t)stream);
+    if (rc != MT_OK) {
+        delete set;
+        return rc;
+    }
+    *out = set;
+    return MT_OK;
+}
+
+int mt_set_attach_reference(mt_set* set, const double* e_ref, const double* w_ref,
+                            const double* f_ref, void* stream) {
+    if (!set) return fail(MT_EINVAL, "set is NULL");
+    if (!e_ref || !w_ref || !f_ref) return fail(MT_EINVAL, "reference pointers must not be NULL");
+    clear_graphs(set);
+    return attach_reference(set, e_ref, w_ref, f_ref, (hipStream_t)stream);
+}
+
+int mt_set_destroy(mt_set* set) {
+    if (set) {
+        (void)hipDeviceSynchronize();
+        delete set;
+    }
+    return MT_OK;
+}
+
+int mt_set_stats(const mt_set* set, int64_t* stats) {
+    if (!set || !stats) return fail(MT_EINVAL, "set and stats must not be NULL");
+    stats[0] = set->S;
+    stats[1] = set->N;
+    stats[2] = set->nb;
+    stats[3] = set->ntrip;
+    stats[4] = set->kmax;
+    stats[5] = set->max_atoms;
+    stats[6] = set->n_batched;
+    stats[7] = set->n_large;
+    return MT_OK;
+}
+
+int mt_set_neighbors(const mt_set* set, int32_t* i, int32_t* j, int32_t* shift, void* stream) {
+    if (!set || !i || !j || !shift) return fail(MT_EINVAL, "NULL argument");
+    return export_neighbors(set, i, j, shift, (hipStream_t)stream);
+}
+
+int tersoff_eval(mt_set* set, const double* x, int P, int precision, int schedule, double* energy,
+                 double* force, double* virial, double* atom_virial, const double* vel,
+                 double* heat_current, void* stream) {
+    TRY(check_common(set, x, P, precision));
+    if (schedule != MT_BATCHED && schedule != MT_PLAIN)
+        return fail(MT_EINVAL, "schedule must be MT_BATCHED or MT_PLAIN");
+    if (heat_current && !vel) return fail(MT_EINVAL, "heat_current needs vel");
+    hipStream_t st = (hipStream_t)stream;
+    TRY(ensure_workspace(set, P, kNVEval));
+    TRY(decode_params(set, x, P, st));
+    if (schedule == MT_BATCHED) {
+        const LaunchCfg cfg = cfg_for(set, P, precision);
+        ItemPlan* plan = get_plan(set, P, cfg, precision);
+        if (!plan) return fail(MT_EHIP, "could not build the work list");
+        TRY(launch_batched(set, *plan, cfg, P, precision, MODE_EVAL, vel, force, atom_virial, st));
+    } else {
+        TRY(launch_plain(set, P, precision, MODE_EVAL, vel, force, atom_virial, st));
+    }
+    TRY(launch_large(set, P, precision, MODE_EVAL, vel, force, atom_virial, st));
+    return launch_finalize_eval(set, P, energy, virial, heat_current, st);
+}
+
+static int fitness_sequence(mt_set* set, const double* x, int P, const double* w, int precision,
+                            int schedule, double* Z, hipStream_t st) {
+    TRY(decode_params(set, x, P, st));
+    if (schedule == MT_BATCHED) {
+        const LaunchCfg cfg = cfg_for(set, P, precision);
+        ItemPlan* plan = get_plan(set, P, cfg, precision);
+        if (!plan) return fail(MT_EHIP, "could not build the work list");
+        TRY(launch_batched(set, *plan, cfg, P, precision, MODE_FIT, nullptr, nullptr, nullptr, st));
+    } else {
+        TRY(launch_plain(set, P, precision, MODE_FIT, nullptr, nullptr, nullptr, st));
+    }
+    TRY(launch_large(set, P, precision, MODE_FIT, nullptr, nullptr, nullptr, st));
+    return launch_finalize_fit(set, P, w, Z, st);
+}
+
+static int check_fitness(mt_set* set, const double* x, int P, const double* w, int precision, double* Z) {
+    TRY(check_common(set, x, P, precision));
+    if (!w || !Z) return fail(MT_EINVAL, "w and Z must not be NULL");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(w[k])) return fail(MT_EINVAL, "weights must be finite");
+    if (!set->has_ref) return fail(MT_ENOREF, "no reference data attached to the set");
+    return MT_OK;
+}
+
+int fitness_eval(mt_set* set, const double* x, int P, const double* w, int precision, int schedule,
+                 double* Z, void* stream) {
+    TRY(check_fitness(set, x, P, w, precision, Z));
+    if (schedule != MT_BATCHED && schedule != MT_PLAIN)
+        return fail(MT_EINVAL, "schedule must be MT_BATCHED or MT_PLAIN");
+    hipStream_t st = (hipStream_t)stream;
+    TRY(ensure_workspace(set, P, kNVFit));
+    if (schedule == MT_PLAIN) return fitness_sequence(set, x, P, w, precision, schedule, Z, st);
+
+    // Batched: replay a captured graph of decode -> batched kernel -> finalize.
+    const LaunchCfg cfg = cfg_for(set, P, precision);
+    if (!get_plan(set, P, cfg, precision)) return fail(MT_EHIP, "could not build the work list");
+    char key[256];
+    snprintf(key, sizeof key, "%p|%p|%d|%d|%.17g|%.17g|%.17g|%d|%d|%d", (const void*)x, (void*)Z, P,
+             precision, w[0], w[1], w[2], cfg.block, cfg.tile, cfg.persistent);
+    auto it = set->graphs.find(key);
+    if (it == set->graphs.end()) {
+        if (!set->capture_stream) HIPCHECK(hipStreamCreateWithFlags(&set->capture_stream, hipStreamNonBlocking));
+        GraphEntry ge;
+        HIPCHECK(hipStreamBeginCapture(set->capture_stream, hipStreamCaptureModeThreadLocal));
+        int rc = fitness_sequence(set, x, P, w, precision, schedule, Z, set->capture_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(set->capture_stream, &graph);
+        if (rc != MT_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        ge.graph = graph;
+        e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        if (set->graphs.size() > 32) clear_graphs(set);
+        it = set->graphs.emplace(key, ge).first;
+    }
+    HIPCHECK(hipGraphLaunch(it->second.exec, st));
+    return MT_OK;
+}
+
+int fitness_grad(mt_set* set, const double* x, int P, const double* w, int precision, double* Z,
+                 double* dZdx, void* stream) {
+    TRY(check_fitness(set, x, P, w, precision, Z));
+    if (!dZdx) return fail(MT_EINVAL, "dZdx must not be NULL");
+    if (set->n_large > 0)
+        return fail(MT_EINVAL, "fitness_grad handles structures of up to " +
+                                   std::to_string(MT_MAX_BATCHED_ATOMS) + " atoms");
+    hipStream_t st = (hipStream_t)stream;
+    TRY(ensure_workspace(set, P, kNVFit));
+    TRY(fitness_sequence(set, x, P, w, precision, MT_BATCHED, Z, st));
+    const LaunchCfg cfg = cfg_for(set, P, precision);
+    ItemPlan* plan = get_plan(set, P, cfg, precision);
+    if (!plan) return fail(MT_EHIP, "could not build the work list");
+    TRY(launch_adjoint(set, *plan, cfg, P, precision, w, Z, st));
+    return launch_finalize_grad(set, P, Z, dZdx, st);
+}
+
+int mt_autotune(mt_set* set, int P, int precision, const char* cache_path) {
+    if (!set) return fail(MT_EINVAL, "set is NULL");
+    if (P <= 0) return fail(MT_EINVAL, "P must be positive");
+    if (precision != MT_FP64 && precision != MT_FP32_ACC64)
+        return fail(MT_EINVAL, "precision must be MT_FP64 or MT_FP32_ACC64");
+    char key[200];
+    snprintf(key, sizeof key, "N=%d S=%d nb=%d trip=%lld P=%d prec=%d", set->N, set->S, set->nb,
+             set->ntrip, P, precision);
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            auto bar = line.find(" | ");
+            if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+            LaunchCfg c;
+            if (sscanf(line.c_str() + bar + 3, "block=%d tile=%d persistent=%d", &c.block, &c.tile,
+                       &c.persistent) == 3 && get_plan(set, P, c, precision)) {
+                set->tuned[{P, precision}] = c;
+                clear_graphs(set);
+                return MT_OK;
+            }
+        }
+    }
+    int maxpad = 8;
+    for (int s = 0; s < set->S; ++s)
+        if (!set->h_large[s]) maxpad = std::max(maxpad, set->h_npad[s]);
+    std::vector<LaunchCfg> cands;
+    for (int block : {64, 128, 256, 512}) {
+        if (block < maxpad) continue;
+        for (int tile : {1, 2, 4, 8, 16, 32, 64, 128}) {
+            if (tile > P && tile != 1) continue;
+            for (int pers : {0, 1}) cands.push_back(LaunchCfg{block, tile, pers});
+        }
+    }
+    if (cands.empty()) return fail(MT_EINVAL, "no batched structures to tune");
+    // timing inputs: Table 2-like parameters for all candidates, zero references if none
+    hipStream_t st;
+    HIPCHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    DevBuf xb;
+    HIPCHECK(xb.reserve(sizeof(double) * 6 * P));
+    std::vector<double> hx(6 * (size_t)P);
+    for (int c = 0; c < P; ++c) {
+        const double base[6] = {3.21481, 1.43134, 2.23801, 0.282818, 0.602568, -0.641048};
+        for (int k = 0; k < 6; ++k) hx[6 * c + k] = base[k] * (1.0 + 0.01 * ((c * 7 + k) % 5));
+    }
+    HIPCHECK(hipMemcpy(xb.p, hx.data(), sizeof(double) * hx.size(), hipMemcpyHostToDevice));
+    if (!set->has_ref) {
+        HIPCHECK(set->fref32.reserve(sizeof(float) * 3 * set->N));
+        HIPCHECK(set->fref64.reserve(sizeof(double) * 3 * set->N));
+        HIPCHECK(hipMemset(set->fref32.p, 0, sizeof(float) * 3 * set->N));
+        HIPCHECK(hipMemset(set->fref64.p, 0, sizeof(double) * 3 * set->N));
+    }
+    int rc = ensure_workspace(set, P, kNVFit);
+    if (rc) { (void)hipStreamDestroy(st); return rc; }
+    rc = decode_params(set, xb.as<double>(), P, st);
+    if (rc) { (void)hipStreamDestroy(st); return rc; }
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    float best = 1e30f;
+    LaunchCfg bestc = cands[0];
+    for (const LaunchCfg& c : cands) {
+        ItemPlan* plan = get_plan(set, P, c, precision);
+        if (!plan) continue;
+        const size_t lds = precision == MT_FP64 ? plan->lds_d : plan->lds_f;
+        if (lds > 160 * 1024) continue;
+        if (launch_batched(set, *plan, c, P, precision, MODE_FIT, nullptr, nullptr, nullptr, st) != MT_OK)
+            continue;
+        float tmin = 1e30f;
+        for (int r = 0; r < 3; ++r) {
+            (void)hipEventRecord(e0, st);
+            (void)launch_batched(set, *plan, c, P, precision, MODE_FIT, nullptr, nullptr, nullptr, st);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            tmin = std::min(tmin, ms);
+        }
+        if (tmin < best) { best = tmin; bestc = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return hip_fail(err, "autotune launches");
+    set->tuned[{P, precision}] = bestc;
+    clear_graphs(set);
+    if (cache_path) {
+        std::ofstream outf(cache_path, std::ios::app);
+        outf << key << " | block=" << bestc.block << " tile=" << bestc.tile
+             << " persistent=" << bestc.persistent << " ms=" << best << "\n";
+    }
+    return MT_OK;
+}
+
+}  // extern "C"

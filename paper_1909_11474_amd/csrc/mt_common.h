@@ -1,0 +1,214 @@
+// Internal declarations shared by the HIP translation units of the library.
+//
+// Data layout in HBM (all "sorted" atom indices: inside each structure the atoms
+// are reordered by descending coordination number, so that the atoms of one
+// wavefront have nearly the same number of neighbours; `perm` maps back to the
+// caller's numbering):
+//
+//   per structure s : st_off[s]     first sorted atom, st_off[S] = N
+//                     st_boff[s]    first bond (CSR over sorted atoms)
+//                     st_npad[s]    atoms rounded up to 8/16/32/64 or a multiple of 64
+//                     st_kmax[s]    largest coordination in s
+//                     st_slot[s]    first partial-sum slot of s
+//   per atom a      : perm[a], nnb[a] (coordination), lbo[a] (first bond of a,
+//                     relative to st_boff[s])
+//   per bond slot   : slot-major arrays [m][N] (m < kcap) of float and double
+//                     geometry: unit vector, length (float: hi+lo split), 1/r,
+//                     f_C(r), f_C'(r); int: reverse bond (structure-local CSR
+//                     index), neighbour atom (structure-local sorted index).
+//
+// Geometry is candidate independent (R1, R2 are fixed, not fitted), so it is
+// built once per structure set and reused by every candidate.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace mt {
+
+constexpr int kMaxNbr = 16;        // template limit on coordination
+constexpr int kMaxBatched = 512;   // largest structure of the batched kernel
+constexpr int kNVFit = 8;          // partial sums per slot: E, W6, |F - F*|^2
+constexpr int kNVEval = 16;        // E, W6, |F-F*|^2, J3, unused
+constexpr int kNVGrad = 8;         // dZ/dx (6), unused (2)
+constexpr int kNParam = 16;        // per-candidate decoded parameter record
+
+// Decoded parameter record (float or double): see decode_params.
+enum ParamIndex {
+    P_AL = 0,       // alpha * log2(e)
+    P_R0HI = 1,     // r0 (float: high part)
+    P_R0LO = 2,     // r0 - r0_hi (float only)
+    P_D0 = 3,
+    P_2D0 = 4,
+    P_ALPHA = 5,
+    P_BETA = 6,
+    P_N = 7,
+    P_NINV2N = 8,   // -1 / (2 n)
+    P_H = 9,
+    P_VALID = 10    // 1 if the candidate is inside the potential's domain
+};
+
+struct Item {       // one (structure, candidate range) work item of the batched kernel
+    int s;
+    int c0;
+    int nc;
+    int cost;       // relative cost used for scheduling
+};
+
+template <typename S>
+struct GeomArrays {
+    const S* ux; const S* uy; const S* uz;
+    const S* rhi; const S* rlo; const S* rinv;
+    const S* fc; const S* fcp;
+};
+
+struct SetDev {
+    int S, N, kcap, nb, nslots;
+    const int* st_off; const int* st_boff; const int* st_npad; const int* st_kmax;
+    const int* st_slot;
+    const int* perm; const int* nnb; const int* lbo;
+    const int* rev; const int* jl;              // [kcap][N]
+    GeomArrays<float> gf;
+    GeomArrays<double> gd;
+    const float* fref32;  const double* fref64; // [3][N] sorted order
+};
+
+// ---------------------------------------------------------------------------
+// Device math.  float: the hardware transcendental instructions (v_exp_f32,
+// v_log_f32, v_rcp_f32); arguments on the hot path stay in the normal range.
+// double: the ROCm device math library.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float dexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float dlog2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float drcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double dexp2(double x) { return exp2(x); }
+__device__ __forceinline__ double dlog2(double x) { return log2(x); }
+__device__ __forceinline__ double drcp(double x) { return 1.0 / x; }
+
+template <typename S>
+struct Consts;
+template <>
+struct Consts<float> {
+    static constexpr float ln2 = 0.693147180559945309f;
+};
+template <>
+struct Consts<double> {
+    static constexpr double ln2 = 0.693147180559945309;
+};
+
+// Forward-mode derivative with respect to the six parameters.
+template <typename S>
+struct Dual {
+    S v;
+    S d[6];
+};
+
+template <typename S>
+__device__ __forceinline__ Dual<S> dconst(S v) {
+    Dual<S> r;
+    r.v = v;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r.d[k] = S(0);
+    return r;
+}
+
+template <typename S> __device__ __forceinline__ S val(S a) { return a; }
+template <typename S> __device__ __forceinline__ S val(const Dual<S>& a) { return a.v; }
+
+template <typename S>
+__device__ __forceinline__ Dual<S> operator+(const Dual<S>& a, const Dual<S>& b) {
+    Dual<S> r; r.v = a.v + b.v;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r.d[k] = a.d[k] + b.d[k];
+    return r;
+}
+template <typename S>
+__device__ __forceinline__ Dual<S> operator-(const Dual<S>& a, const Dual<S>& b) {
+    Dual<S> r; r.v = a.v - b.v;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r.d[k] = a.d[k] - b.d[k];
+    return r;
+}
+template <typename S>
+__device__ __forceinline__ Dual<S> operator-(const Dual<S>& a) {
+    Dual<S> r; r.v = -a.v;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r.d[k] = -a.d[k];
+    return r;
+}
+template <typename S>
+__device__ __forceinline__ Dual<S> operator*(const Dual<S>& a, const Dual<S>& b) {
+    Dual<S> r; r.v = a.v * b.v;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+    return r;
+}
+template <typename S>
+__device__ __forceinline__ Dual<S> operator*(const Dual<S>& a, S b) {
+    Dual<S> r; r.v = a.v * b;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r.d[k] = a.d[k] * b;
+    return r;
+}
+template <typename S>
+__device__ __forceinline__ Dual<S> operator*(S b, const Dual<S>& a) { return a * b; }
+template <typename S>
+__device__ __forceinline__ Dual<S> operator+(const Dual<S>& a, S b) {
+    Dual<S> r = a; r.v += b; return r;
+}
+template <typename S>
+__device__ __forceinline__ Dual<S> operator+(S b, const Dual<S>& a) { return a + b; }
+template <typename S>
+__device__ __forceinline__ Dual<S> operator-(const Dual<S>& a, S b) {
+    Dual<S> r = a; r.v -= b; return r;
+}
+template <typename S>
+__device__ __forceinline__ Dual<S> operator-(S b, const Dual<S>& a) { return (-a) + b; }
+template <typename S>
+__device__ __forceinline__ Dual<S> dexp2(const Dual<S>& a) {
+    Dual<S> r; r.v = dexp2(a.v);
+    const S g = r.v * Consts<S>::ln2;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r.d[k] = g * a.d[k];
+    return r;
+}
+template <typename S>
+__device__ __forceinline__ Dual<S> dlog2(const Dual<S>& a) {
+    Dual<S> r; r.v = dlog2(a.v);
+    const S g = drcp(a.v * Consts<S>::ln2);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r.d[k] = g * a.d[k];
+    return r;
+}
+template <typename S>
+__device__ __forceinline__ Dual<S> drcp(const Dual<S>& a) {
+    Dual<S> r; r.v = drcp(a.v);
+    const S g = -r.v * r.v;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r.d[k] = g * a.d[k];
+    return r;
+}
+template <typename S>
+__device__ __forceinline__ Dual<S> dselect(bool c, const Dual<S>& a, const Dual<S>& b) {
+    Dual<S> r; r.v = c ? a.v : b.v;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r.d[k] = c ? a.d[k] : b.d[k];
+    return r;
+}
+template <typename S>
+__device__ __forceinline__ S dselect(bool c, S a, S b) { return c ? a : b; }
+
+template <typename V, typename S>
+__device__ __forceinline__ V vconst(S v) {
+    if constexpr (sizeof(V) == sizeof(S)) return v; else return dconst<S>(v);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side helpers shared by the translation units.
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+}  // namespace mt

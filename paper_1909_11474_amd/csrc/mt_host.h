@@ -1,0 +1,135 @@
+// Host-side state of a structure set and the launch entry points of each
+// translation unit.
+#pragma once
+
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "mt_common.h"
+#include "mt_tersoff.h"
+
+namespace mt {
+
+// Device buffer owned by the library.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    // Grow to at least `n` bytes (contents are not preserved).
+    hipError_t reserve(size_t n) {
+        if (n <= bytes && p) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, n < 256 ? 256 : n);
+        if (e == hipSuccess) bytes = n < 256 ? 256 : n;
+        return e;
+    }
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct LaunchCfg {            // launch shape of the batched kernel
+    int block = 0;            // threads per block, multiple of 64, >= largest padded structure
+    int tile = 0;             // candidates per work item (0: derived from the block)
+    int persistent = 0;       // 1: static LPT bins over a fixed grid; 0: one block per item
+};
+
+struct ItemPlan {             // uploaded work list for one (P, cfg)
+    DevBuf items;             // Item[n_items]
+    DevBuf bin_off;           // int[n_bins + 1]
+    int n_items = 0;
+    int n_bins = 0;
+    size_t lds_f = 0, lds_d = 0;   // dynamic LDS bytes for float / double
+};
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace mt
+
+struct mt_set {
+    int S = 0, N = 0, kcap = 0, kmax = 0, nb = 0, nslots = 0;
+    long long ntrip = 0;
+    int max_atoms = 0, n_batched = 0, n_large = 0;
+    double R1 = 0, R2 = 0;
+    int device = 0;
+
+    // host copies of per-structure tables
+    std::vector<int> h_off, h_boff, h_npad, h_kmax, h_slot, h_large;
+    std::vector<long long> h_trip;           // ordered triplets per structure
+
+    // device data (see mt_common.h for the layout)
+    mt::DevBuf pos, cell;
+    mt::DevBuf st_off, st_boff, st_npad, st_kmax, st_slot;
+    mt::DevBuf perm, nnb, lbo, rev, jl;
+    mt::DevBuf nbr_j, nbr_sh;                // caller-numbering neighbour entries, [kcap][N]
+    mt::DevBuf gf, gd;                       // float / double geometry, 8 resp. 7 arrays of [kcap][N]
+    mt::DevBuf gf_rlo;                       // float low part of r, [kcap][N]
+
+    // references (sorted order)
+    bool has_ref = false;
+    mt::DevBuf eref, wref, fref32, fref64;
+    double Q[3] = {0, 0, 0};
+
+    // workspaces
+    mt::DevBuf params_f, params_d;           // [P][kNParam]
+    mt::DevBuf partial;                      // [P][nslots][NV] double
+    mt::DevBuf partial2;                     // gradient partials
+    mt::DevBuf zwork;                        // [P][4] scratch for fitness_grad
+    mt::DevBuf gbuf;                         // large path bond gradients
+    mt::DevBuf scalars;                      // small device scratch
+
+    std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<mt::ItemPlan>> plans;
+    std::map<std::pair<int, int>, mt::LaunchCfg> tuned;     // (P, precision) -> cfg
+    std::map<std::string, mt::GraphEntry> graphs;
+    hipStream_t capture_stream = nullptr;
+
+    mt::SetDev dev() const;
+    ~mt_set();
+};
+
+namespace mt {
+
+// mt_set.hip
+int build_set(mt_set* set, const int64_t* atom_offset, const double* pos, const double* cell,
+              hipStream_t stream);
+int attach_reference(mt_set* set, const double* e_ref, const double* w_ref, const double* f_ref,
+                     hipStream_t stream);
+int export_neighbors(const mt_set* set, int32_t* i, int32_t* j, int32_t* shift, hipStream_t stream);
+
+// mt_eval.hip
+int decode_params(mt_set* set, const double* x, int P, hipStream_t stream);
+int launch_batched(mt_set* set, const ItemPlan& plan, const LaunchCfg& cfg, int P, int precision,
+                   int mode, const double* vel, double* force, double* atom_virial,
+                   hipStream_t stream);
+int launch_plain(mt_set* set, int P, int precision, int mode, const double* vel, double* force,
+                 double* atom_virial, hipStream_t stream);
+int launch_large(mt_set* set, int P, int precision, int mode, const double* vel, double* force,
+                 double* atom_virial, hipStream_t stream);
+int launch_finalize_fit(mt_set* set, int P, const double* w, double* Z, hipStream_t stream);
+int launch_finalize_eval(mt_set* set, int P, double* energy, double* virial, double* heat,
+                         hipStream_t stream);
+int launch_adjoint(mt_set* set, const ItemPlan& plan, const LaunchCfg& cfg, int P, int precision,
+                   const double* w, const double* Z, hipStream_t stream);
+int launch_adjoint_plain(mt_set* set, int P, int precision, const double* w, const double* Z,
+                         hipStream_t stream);
+int launch_finalize_grad(mt_set* set, int P, const double* Z, double* dZdx, hipStream_t stream);
+
+enum Mode { MODE_FIT = 0, MODE_EVAL = 1 };
+
+ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int precision);
+LaunchCfg default_cfg(const mt_set* set, int P, int precision);
+size_t lds_bytes(const mt_set* set, int block, int elem);
+
+}  // namespace mt

@@ -76,6 +76,8 @@ enum mt_schedule {
 /* Largest structure handled by the batched kernels; bigger structures take the
  * two-pass large-system kernels. */
 #define MT_MAX_BATCHED_ATOMS 512
+/* Largest coordination number handled by fitness_grad. */
+#define MT_MAX_GRAD_NBR 12
 
 /*
  * Build a structure set: copies the structures and finds, on the GPU with a
@@ -169,7 +171,8 @@ int fitness_eval(mt_set* set, const double* x, int P, const double* w, int preci
  * Fitness and its gradient dZ/dx with respect to the six parameters (the
  * derivative of the Sec. III.B fitness, including the force and virial terms,
  * which need mixed second derivatives of the energy).  A term with Z_x = 0
- * contributes no gradient.
+ * contributes no gradient.  Structures must have at most MT_MAX_BATCHED_ATOMS
+ * atoms and coordination numbers up to MT_MAX_GRAD_NBR; otherwise MT_EINVAL.
  *   Z     device [P][4]
  *   dZdx  device [P][6]
  */
@@ -184,6 +187,19 @@ int fitness_grad(mt_set* set, const double* x, int P, const double* w, int preci
  * matching entry already there is used without timing.
  */
 int mt_autotune(mt_set* set, int P, int precision, const char* cache_path);
+
+/*
+ * Kernel timing for measurement.  While enabled, every launch of the batched
+ * evaluation kernel (and of the adjoint kernel) is bracketed by HIP events on
+ * the stream it is launched on, and calls run without graph replay.
+ * mt_profile_read synchronises those events and returns, per kernel kind
+ * (0 = batched evaluation, 1 = adjoint), the summed duration in milliseconds
+ * and the number of launches since the last read, then resets the counters.
+ *   ms        host double [2]
+ *   launches  host int64 [2]
+ */
+int mt_profile_enable(mt_set* set, int enable);
+int mt_profile_read(mt_set* set, double* ms, int64_t* launches);
 
 /* Message for the calling thread's most recent error (never NULL). */
 const char* mt_last_error(void);

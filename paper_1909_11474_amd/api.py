@@ -186,6 +186,12 @@ class TersoffSet:
         L.check(rc, "fitness_eval")
         return Z
 
+    def fitness_call(self, x: torch.Tensor, Z: torch.Tensor, weights=(1.0, 1.0, 1.0),
+                     precision="fp32", schedule="batched") -> "FitnessCall":
+        """A pre-marshalled fitness_eval(x -> Z) for repeated calls on the same
+        device buffers (a GA generation loop): the arguments are converted once."""
+        return FitnessCall(self, x, Z, weights, precision, schedule)
+
     def fitness_grad(self, x, weights=(1.0, 1.0, 1.0), precision="fp32"):
         """(Z [P, 4], dZ/dx [P, 6]) as device tensors."""
         xt = self._x(x)
@@ -199,11 +205,49 @@ class TersoffSet:
         L.check(rc, "fitness_grad")
         return Z, G
 
+    def profile(self, enable: bool = True):
+        """Bracket each batched / adjoint kernel launch with HIP events."""
+        L.check(self._lib.mt_profile_enable(self._handle, 1 if enable else 0), "mt_profile_enable")
+
+    def profile_read(self):
+        """{'batched': (ms, launches), 'adjoint': (ms, launches)} since the last read."""
+        ms = (ctypes.c_double * 2)()
+        n = (ctypes.c_int64 * 2)()
+        L.check(self._lib.mt_profile_read(self._handle, ms, n), "mt_profile_read")
+        return {"batched": (ms[0], int(n[0])), "adjoint": (ms[1], int(n[1]))}
+
     def autotune(self, P: int, precision="fp32", cache_path: Optional[str] = None):
         with torch.cuda.device(self.device):
             rc = self._lib.mt_autotune(self._handle, int(P), _prec(precision),
                                        cache_path.encode() if cache_path else None)
         L.check(rc, "mt_autotune")
+
+
+class FitnessCall:
+    """fitness_eval bound to fixed device tensors x [P, 6] and Z [P, 4] (float64,
+    contiguous, on the set's device).  Calling it enqueues one evaluation on the
+    current stream; the contents of x may change between calls."""
+
+    def __init__(self, tset: TersoffSet, x: torch.Tensor, Z: torch.Tensor, weights, precision, schedule):
+        if not (torch.is_tensor(x) and x.dtype == torch.float64 and x.is_contiguous()
+                and x.device == tset.device and x.dim() == 2 and x.shape[1] == 6):
+            raise ValueError("x must be a contiguous float64 [P, 6] tensor on the set's device")
+        P = x.shape[0]
+        if not (torch.is_tensor(Z) and Z.dtype == torch.float64 and Z.is_contiguous()
+                and Z.device == tset.device and tuple(Z.shape) == (P, 4)):
+            raise ValueError("Z must be a contiguous float64 [P, 4] tensor on the set's device")
+        self.tset, self.x, self.Z = tset, x, Z
+        self._fn = tset._lib.fitness_eval
+        self._w = (ctypes.c_double * 3)(*[float(v) for v in weights])
+        self._args = (tset._handle, ctypes.c_void_p(x.data_ptr()), int(P), self._w,
+                      _prec(precision), _sched(schedule), ctypes.c_void_p(Z.data_ptr()))
+
+    def __call__(self, stream: Optional[torch.cuda.Stream] = None):
+        s = stream if stream is not None else torch.cuda.current_stream(self.tset.device)
+        rc = self._fn(*self._args, ctypes.c_void_p(s.cuda_stream))
+        if rc:
+            L.check(rc, "fitness_eval")
+        return self.Z
 
 
 def from_structures(structs, R1: float = 2.8, R2: float = 3.2, max_nbr: int = L.MT_MAX_NBR,

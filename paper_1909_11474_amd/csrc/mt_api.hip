@@ -52,25 +52,26 @@ mt::SetDev mt_set::dev() const {
     SetDev d{};
     d.S = S; d.N = N; d.kcap = kcap; d.nb = nb; d.nslots = nslots;
     d.st_off = st_off.as<int>(); d.st_boff = st_boff.as<int>(); d.st_npad = st_npad.as<int>();
-    d.st_kmax = st_kmax.as<int>(); d.st_slot = st_slot.as<int>();
-    d.perm = perm.as<int>(); d.nnb = nnb.as<int>(); d.lbo = lbo.as<int>();
-    d.rev = rev.as<int>(); d.jl = jl.as<int>();
+    d.st_kmax = st_kmax.as<int>(); d.st_slot = st_slot.as<int>(); d.st_xsize = st_xsize.as<int>();
+    d.perm = perm.as<int>(); d.nnb = nnb.as<int>(); d.lbo = lbo.as<int>(); d.xbase = xbase.as<int>();
+    d.rev = rev.as<int>(); d.revc = revc.as<int>(); d.jl = jl.as<int>();
     const size_t KN = (size_t)kcap * N;
     const float* f = gf.as<float>();
+    const float4* pk = gpk.as<float4>();
     d.gf = GeomArrays<float>{f, f + KN, f + 2 * KN, f + 3 * KN, gf_rlo.as<float>(), f + 4 * KN,
-                             f + 5 * KN, f + 6 * KN};
+                             f + 5 * KN, f + 6 * KN, pk, pk + KN};
     const double* g = gd.as<double>();
     d.gd = GeomArrays<double>{g, g + KN, g + 2 * KN, g + 3 * KN, nullptr, g + 4 * KN,
-                              g + 5 * KN, g + 6 * KN};
+                              g + 5 * KN, g + 6 * KN, nullptr, nullptr};
     d.fref32 = fref32.as<float>();
     d.fref64 = fref64.as<double>();
     return d;
 }
 
 static void clear_graphs(mt_set* set) {
-    for (auto& kv : set->graphs) {
-        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
-        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    for (auto& g : set->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
     }
     set->graphs.clear();
 }
@@ -78,15 +79,42 @@ static void clear_graphs(mt_set* set) {
 mt_set::~mt_set() {
     clear_graphs(this);
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    for (auto& v : prof_events)
+        for (auto& pr : v) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
 }
+
+namespace mt {
+
+static hipEvent_t pool_event(mt_set* set) {
+    if (!set->event_pool.empty()) {
+        hipEvent_t e = set->event_pool.back();
+        set->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+ProfScope::ProfScope(mt_set* set, int kind) {
+    if (!set->profiling) return;
+    e0 = pool_event(set);
+    e1 = pool_event(set);
+    if (!e0 || !e1) { e0 = e1 = nullptr; return; }
+    set->prof_events[kind].push_back({e0, e1});
+}
+
+}  // namespace mt
 
 // Reserve per-call workspaces; any reallocation invalidates captured graphs.
 static int ensure_workspace(mt_set* set, int P, int nv) {
-    const void* before[2] = {set->params_d.p, set->partial.p};
-    HIPCHECK(set->params_f.reserve(sizeof(float) * kNParam * (size_t)P));
-    HIPCHECK(set->params_d.reserve(sizeof(double) * kNParam * (size_t)P));
+    const void* before = set->partial.p;
     HIPCHECK(set->partial.reserve(sizeof(double) * nv * (size_t)P * std::max(1, set->nslots)));
-    if (before[0] != set->params_d.p || before[1] != set->partial.p) clear_graphs(set);
+    if (before != set->partial.p) clear_graphs(set);
     return MT_OK;
 }
 
@@ -188,12 +216,10 @@ int tersoff_eval(mt_set* set, const double* x, int P, int precision, int schedul
     if (heat_current && !vel) return fail(MT_EINVAL, "heat_current needs vel");
     hipStream_t st = (hipStream_t)stream;
     TRY(ensure_workspace(set, P, kNVEval));
-    TRY(decode_params(set, x, P, st));
+    set->cur_x = x;
     if (schedule == MT_BATCHED) {
         const LaunchCfg cfg = cfg_for(set, P, precision);
-        ItemPlan* plan = get_plan(set, P, cfg, precision);
-        if (!plan) return fail(MT_EHIP, "could not build the work list");
-        TRY(launch_batched(set, *plan, cfg, P, precision, MODE_EVAL, vel, force, atom_virial, st));
+        TRY(launch_batched(set, cfg, P, precision, MODE_EVAL, vel, force, atom_virial, st));
     } else {
         TRY(launch_plain(set, P, precision, MODE_EVAL, vel, force, atom_virial, st));
     }
@@ -203,12 +229,10 @@ int tersoff_eval(mt_set* set, const double* x, int P, int precision, int schedul
 
 static int fitness_sequence(mt_set* set, const double* x, int P, const double* w, int precision,
                             int schedule, double* Z, hipStream_t st) {
-    TRY(decode_params(set, x, P, st));
+    set->cur_x = x;
     if (schedule == MT_BATCHED) {
         const LaunchCfg cfg = cfg_for(set, P, precision);
-        ItemPlan* plan = get_plan(set, P, cfg, precision);
-        if (!plan) return fail(MT_EHIP, "could not build the work list");
-        TRY(launch_batched(set, *plan, cfg, P, precision, MODE_FIT, nullptr, nullptr, nullptr, st));
+        TRY(launch_batched(set, cfg, P, precision, MODE_FIT, nullptr, nullptr, nullptr, st));
     } else {
         TRY(launch_plain(set, P, precision, MODE_FIT, nullptr, nullptr, nullptr, st));
     }
@@ -232,18 +256,24 @@ int fitness_eval(mt_set* set, const double* x, int P, const double* w, int preci
         return fail(MT_EINVAL, "schedule must be MT_BATCHED or MT_PLAIN");
     hipStream_t st = (hipStream_t)stream;
     TRY(ensure_workspace(set, P, kNVFit));
-    if (schedule == MT_PLAIN) return fitness_sequence(set, x, P, w, precision, schedule, Z, st);
+    if (schedule == MT_PLAIN || set->profiling)
+        return fitness_sequence(set, x, P, w, precision, schedule, Z, st);
 
-    // Batched: replay a captured graph of decode -> batched kernel -> finalize.
+    // Batched: replay a captured graph of the batched kernel(s) and finalize.
     const LaunchCfg cfg = cfg_for(set, P, precision);
-    if (!get_plan(set, P, cfg, precision)) return fail(MT_EHIP, "could not build the work list");
-    char key[256];
-    snprintf(key, sizeof key, "%p|%p|%d|%d|%.17g|%.17g|%.17g|%d|%d|%d", (const void*)x, (void*)Z, P,
-             precision, w[0], w[1], w[2], cfg.block, cfg.tile, cfg.persistent);
-    auto it = set->graphs.find(key);
-    if (it == set->graphs.end()) {
+    GraphKey key;
+    key.x = x; key.Z = Z; key.P = P; key.precision = precision;
+    key.block = cfg.block; key.tile = cfg.tile; key.persistent = cfg.persistent;
+    key.w[0] = w[0]; key.w[1] = w[1]; key.w[2] = w[2];
+    size_t hit = set->graphs.size();
+    for (size_t i = 0; i < set->graphs.size(); ++i)
+        if (set->graphs[i].key == key) { hit = i; break; }
+    if (hit == set->graphs.size()) {
+        if (!get_plan(set, P, cfg, precision == MT_FP64 ? FAM_FIT64 : FAM_FIT32))
+            return fail(MT_EINVAL, "could not build the work list");
         if (!set->capture_stream) HIPCHECK(hipStreamCreateWithFlags(&set->capture_stream, hipStreamNonBlocking));
         GraphEntry ge;
+        ge.key = key;
         HIPCHECK(hipStreamBeginCapture(set->capture_stream, hipStreamCaptureModeThreadLocal));
         int rc = fitness_sequence(set, x, P, w, precision, schedule, Z, set->capture_stream);
         hipGraph_t graph = nullptr;
@@ -259,10 +289,19 @@ int fitness_eval(mt_set* set, const double* x, int P, const double* w, int preci
             (void)hipGraphDestroy(graph);
             return hip_fail(e, "hipGraphInstantiate");
         }
-        if (set->graphs.size() > 32) clear_graphs(set);
-        it = set->graphs.emplace(key, ge).first;
+        if (set->graphs.size() >= 16) {
+            GraphEntry& old = set->graphs.back();
+            (void)hipGraphExecDestroy(old.exec);
+            (void)hipGraphDestroy(old.graph);
+            set->graphs.pop_back();
+        }
+        set->graphs.insert(set->graphs.begin(), ge);
+        hit = 0;
+    } else if (hit != 0) {
+        std::swap(set->graphs[0], set->graphs[hit]);
+        hit = 0;
     }
-    HIPCHECK(hipGraphLaunch(it->second.exec, st));
+    HIPCHECK(hipGraphLaunch(set->graphs[0].exec, st));
     return MT_OK;
 }
 
@@ -273,14 +312,40 @@ int fitness_grad(mt_set* set, const double* x, int P, const double* w, int preci
     if (set->n_large > 0)
         return fail(MT_EINVAL, "fitness_grad handles structures of up to " +
                                    std::to_string(MT_MAX_BATCHED_ATOMS) + " atoms");
+    if (set->kmax > MT_MAX_GRAD_NBR)
+        return fail(MT_EINVAL, "fitness_grad handles coordination numbers up to " +
+                                   std::to_string(MT_MAX_GRAD_NBR));
     hipStream_t st = (hipStream_t)stream;
     TRY(ensure_workspace(set, P, kNVFit));
     TRY(fitness_sequence(set, x, P, w, precision, MT_BATCHED, Z, st));
     const LaunchCfg cfg = cfg_for(set, P, precision);
-    ItemPlan* plan = get_plan(set, P, cfg, precision);
-    if (!plan) return fail(MT_EHIP, "could not build the work list");
-    TRY(launch_adjoint(set, *plan, cfg, P, precision, w, Z, st));
+    TRY(launch_adjoint(set, cfg, P, precision, w, Z, st));
     return launch_finalize_grad(set, P, Z, dZdx, st);
+}
+
+int mt_profile_enable(mt_set* set, int enable) {
+    if (!set) return fail(MT_EINVAL, "set is NULL");
+    set->profiling = enable != 0;
+    return MT_OK;
+}
+
+int mt_profile_read(mt_set* set, double* ms, int64_t* launches) {
+    if (!set || !ms || !launches) return fail(MT_EINVAL, "NULL argument");
+    for (int k = 0; k < 2; ++k) {
+        double tot = 0.0;
+        for (auto& pr : set->prof_events[k]) {
+            HIPCHECK(hipEventSynchronize(pr.second));
+            float t = 0.f;
+            HIPCHECK(hipEventElapsedTime(&t, pr.first, pr.second));
+            tot += t;
+            set->event_pool.push_back(pr.first);
+            set->event_pool.push_back(pr.second);
+        }
+        ms[k] = tot;
+        launches[k] = (int64_t)set->prof_events[k].size();
+        set->prof_events[k].clear();
+    }
+    return MT_OK;
 }
 
 int mt_autotune(mt_set* set, int P, int precision, const char* cache_path) {
@@ -288,6 +353,7 @@ int mt_autotune(mt_set* set, int P, int precision, const char* cache_path) {
     if (P <= 0) return fail(MT_EINVAL, "P must be positive");
     if (precision != MT_FP64 && precision != MT_FP32_ACC64)
         return fail(MT_EINVAL, "precision must be MT_FP64 or MT_FP32_ACC64");
+    const int fam = precision == MT_FP64 ? FAM_FIT64 : FAM_FIT32;
     char key[200];
     snprintf(key, sizeof key, "N=%d S=%d nb=%d trip=%lld P=%d prec=%d", set->N, set->S, set->nb,
              set->ntrip, P, precision);
@@ -299,7 +365,7 @@ int mt_autotune(mt_set* set, int P, int precision, const char* cache_path) {
             if (bar == std::string::npos || line.substr(0, bar) != key) continue;
             LaunchCfg c;
             if (sscanf(line.c_str() + bar + 3, "block=%d tile=%d persistent=%d", &c.block, &c.tile,
-                       &c.persistent) == 3 && get_plan(set, P, c, precision)) {
+                       &c.persistent) == 3 && get_plan(set, P, c, fam)) {
                 set->tuned[{P, precision}] = c;
                 clear_graphs(set);
                 return MT_OK;
@@ -312,7 +378,9 @@ int mt_autotune(mt_set* set, int P, int precision, const char* cache_path) {
     std::vector<LaunchCfg> cands;
     for (int block : {64, 128, 256, 512}) {
         if (block < maxpad) continue;
-        for (int tile : {1, 2, 4, 8, 16, 32, 64, 128}) {
+        // powers of two plus tiles that let a whole generation fit in one
+        // round of resident wavefronts for common population sizes
+        for (int tile : {1, 2, 4, 8, 12, 16, 20, 24, 32, 40, 48, 64, 80, 128}) {
             if (tile > P && tile != 1) continue;
             for (int pers : {0, 1}) cands.push_back(LaunchCfg{block, tile, pers});
         }
@@ -337,24 +405,37 @@ int mt_autotune(mt_set* set, int P, int precision, const char* cache_path) {
     }
     int rc = ensure_workspace(set, P, kNVFit);
     if (rc) { (void)hipStreamDestroy(st); return rc; }
-    rc = decode_params(set, xb.as<double>(), P, st);
-    if (rc) { (void)hipStreamDestroy(st); return rc; }
+    set->cur_x = xb.as<double>();
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
+    DevBuf zb;
+    HIPCHECK(zb.reserve(sizeof(double) * 4 * (size_t)P));
+    const double wt[3] = {1.0, 1.0, 1.0};
     float best = 1e30f;
     LaunchCfg bestc = cands[0];
+    const bool have_ref = set->has_ref;
+    auto saved = set->tuned.find({P, precision});
+    const bool had = saved != set->tuned.end();
+    const LaunchCfg prev = had ? saved->second : LaunchCfg{};
     for (const LaunchCfg& c : cands) {
-        ItemPlan* plan = get_plan(set, P, c, precision);
+        ItemPlan* plan = get_plan(set, P, c, fam);
         if (!plan) continue;
-        const size_t lds = precision == MT_FP64 ? plan->lds_d : plan->lds_f;
+        size_t lds = 0;
+        for (auto& cp : plan->cls) lds = std::max(lds, cp->lds);
         if (lds > 160 * 1024) continue;
-        if (launch_batched(set, *plan, c, P, precision, MODE_FIT, nullptr, nullptr, nullptr, st) != MT_OK)
-            continue;
+        set->tuned[{P, precision}] = c;
+        // one generation: batched kernel(s) and the finalize kernel
+        auto gen = [&]() -> int {
+            if (have_ref)
+                return fitness_sequence(set, xb.as<double>(), P, wt, precision, MT_BATCHED, zb.as<double>(), st);
+            return launch_batched(set, c, P, precision, MODE_FIT, nullptr, nullptr, nullptr, st);
+        };
+        if (gen() != MT_OK) continue;
         float tmin = 1e30f;
         for (int r = 0; r < 3; ++r) {
             (void)hipEventRecord(e0, st);
-            (void)launch_batched(set, *plan, c, P, precision, MODE_FIT, nullptr, nullptr, nullptr, st);
+            (void)gen();
             (void)hipEventRecord(e1, st);
             (void)hipEventSynchronize(e1);
             float ms = 0;
@@ -362,7 +443,13 @@ int mt_autotune(mt_set* set, int P, int precision, const char* cache_path) {
             tmin = std::min(tmin, ms);
         }
         if (tmin < best) { best = tmin; bestc = c; }
+        if (cache_path) {
+            std::ofstream logf(cache_path, std::ios::app);
+            logf << "# " << key << " | block=" << c.block << " tile=" << c.tile << " persistent="
+                 << c.persistent << " ms=" << tmin << "\n";
+        }
     }
+    if (had) set->tuned[{P, precision}] = prev; else set->tuned.erase({P, precision});
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(st);

@@ -11,11 +11,18 @@
 //                     st_kmax[s]    largest coordination in s
 //                     st_slot[s]    first partial-sum slot of s
 //   per atom a      : perm[a], nnb[a] (coordination), lbo[a] (first bond of a,
-//                     relative to st_boff[s])
+//                     relative to st_boff[s]), xbase[a] (exchange slot, below)
 //   per bond slot   : slot-major arrays [m][N] (m < kcap) of float and double
 //                     geometry: unit vector, length (float: hi+lo split), 1/r,
-//                     f_C(r), f_C'(r); int: reverse bond (structure-local CSR
-//                     index), neighbour atom (structure-local sorted index).
+//                     f_C(r), f_C'(r); int: exchange slot and CSR index of the
+//                     reverse bond, neighbour atom (structure-local sorted index).
+//
+// Exchange slots (LDS of the batched kernels).  A replica of structure s is cut
+// into chunks of G = min(npad, 64) lanes; chunk c reserves K_c * G slots, K_c
+// being the largest coordination in the chunk (at least the lowest variant of
+// the structure's class), and bond m of the atom in lane l of the chunk uses
+// slot off_c + m * G + l.  Padded bonds (m >= coordination) own a slot too and
+// their reverse index is that slot, so the exchange needs no predicates.
 //
 // Geometry is candidate independent (R1, R2 are fixed, not fitted), so it is
 // built once per structure set and reused by every candidate.
@@ -35,7 +42,7 @@ constexpr int kNVEval = 16;        // E, W6, |F-F*|^2, J3, unused
 constexpr int kNVGrad = 8;         // dZ/dx (6), unused (2)
 constexpr int kNParam = 16;        // per-candidate decoded parameter record
 
-// Decoded parameter record (float or double): see decode_params.
+// Decoded parameter record (float or double), filled per work item in LDS.
 enum ParamIndex {
     P_AL = 0,       // alpha * log2(e)
     P_R0HI = 1,     // r0 (float: high part)
@@ -62,14 +69,21 @@ struct GeomArrays {
     const S* ux; const S* uy; const S* uz;
     const S* rhi; const S* rlo; const S* rinv;
     const S* fc; const S* fcp;
+    // float only: the same geometry packed per bond slot as two 4-vectors,
+    // (ux, uy, uz, r_hi) and (r_lo, 1/r, f_C, f_C'), [kcap][N] each
+    const float4* pk0; const float4* pk1;
 };
 
 struct SetDev {
     int S, N, kcap, nb, nslots;
     const int* st_off; const int* st_boff; const int* st_npad; const int* st_kmax;
     const int* st_slot;
+    const int* st_xsize;                        // exchange slots of one replica
     const int* perm; const int* nnb; const int* lbo;
-    const int* rev; const int* jl;              // [kcap][N]
+    const int* xbase;                           // [N] first exchange slot of the atom
+    const int* rev;                             // [kcap][N] exchange slot of the reverse bond
+    const int* revc;                            // [kcap][N] structure-local CSR index of it
+    const int* jl;                              // [kcap][N] structure-local neighbour atom
     GeomArrays<float> gf;
     GeomArrays<double> gd;
     const float* fref32;  const double* fref64; // [3][N] sorted order

@@ -43,15 +43,38 @@ struct LaunchCfg {            // launch shape of the batched kernel
     int persistent = 0;       // 1: static LPT bins over a fixed grid; 0: one block per item
 };
 
-struct ItemPlan {             // uploaded work list for one (P, cfg)
+struct ClassPlan {            // work list of one coordination class
+    int mc = 0;               // class: largest coordination the kernel instance serves
     DevBuf items;             // Item[n_items]
     DevBuf bin_off;           // int[n_bins + 1]
+    std::vector<Item> h_items;
     int n_items = 0;
     int n_bins = 0;
-    size_t lds_f = 0, lds_d = 0;   // dynamic LDS bytes for float / double
+    int ptile = 1;            // largest candidate count of an item
+    size_t lds = 0;           // dynamic LDS bytes
+};
+
+struct ItemPlan {             // uploaded work lists for one (P, launch shape, kernel family)
+    std::vector<std::unique_ptr<ClassPlan>> cls;
+};
+
+// Kernel families: precision x (fitness, energy/force/virial, adjoint).
+enum Family { FAM_FIT32 = 0, FAM_EVAL32, FAM_FIT64, FAM_EVAL64, FAM_ADJ32, FAM_ADJ64, NFAM };
+
+struct GraphKey {             // what a captured fitness graph depends on
+    const void* x = nullptr;
+    void* Z = nullptr;
+    int P = 0, precision = 0, block = 0, tile = 0, persistent = 0;
+    double w[3] = {0, 0, 0};
+    bool operator==(const GraphKey& o) const {
+        return x == o.x && Z == o.Z && P == o.P && precision == o.precision && block == o.block &&
+               tile == o.tile && persistent == o.persistent && w[0] == o.w[0] && w[1] == o.w[1] &&
+               w[2] == o.w[2];
+    }
 };
 
 struct GraphEntry {
+    GraphKey key;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -66,24 +89,27 @@ struct mt_set {
     int device = 0;
 
     // host copies of per-structure tables
-    std::vector<int> h_off, h_boff, h_npad, h_kmax, h_slot, h_large;
+    std::vector<int> h_off, h_boff, h_npad, h_kmax, h_slot, h_large, h_xsize;
     std::vector<long long> h_trip;           // ordered triplets per structure
 
     // device data (see mt_common.h for the layout)
     mt::DevBuf pos, cell;
-    mt::DevBuf st_off, st_boff, st_npad, st_kmax, st_slot;
-    mt::DevBuf perm, nnb, lbo, rev, jl;
+    mt::DevBuf st_off, st_boff, st_npad, st_kmax, st_slot, st_xsize;
+    mt::DevBuf perm, nnb, lbo, xbase, rev, revc, jl;
     mt::DevBuf nbr_j, nbr_sh;                // caller-numbering neighbour entries, [kcap][N]
     mt::DevBuf gf, gd;                       // float / double geometry, 8 resp. 7 arrays of [kcap][N]
     mt::DevBuf gf_rlo;                       // float low part of r, [kcap][N]
+    mt::DevBuf gpk;                          // float geometry packed as 2 x float4, [2][kcap][N]
 
     // references (sorted order)
     bool has_ref = false;
     mt::DevBuf eref, wref, fref32, fref64;
     double Q[3] = {0, 0, 0};
 
+    // parameter sets of the call being enqueued (device [P][6])
+    const double* cur_x = nullptr;
+
     // workspaces
-    mt::DevBuf params_f, params_d;           // [P][kNParam]
     mt::DevBuf partial;                      // [P][nslots][NV] double
     mt::DevBuf partial2;                     // gradient partials
     mt::DevBuf zwork;                        // [P][4] scratch for fitness_grad
@@ -92,8 +118,13 @@ struct mt_set {
 
     std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<mt::ItemPlan>> plans;
     std::map<std::pair<int, int>, mt::LaunchCfg> tuned;     // (P, precision) -> cfg
-    std::map<std::string, mt::GraphEntry> graphs;
+    std::vector<mt::GraphEntry> graphs;      // most recently used first
     hipStream_t capture_stream = nullptr;
+
+    // kernel timing (mt_profile_enable): event pairs per kernel kind
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events[2];
+    std::vector<hipEvent_t> event_pool;
 
     mt::SetDev dev() const;
     ~mt_set();
@@ -109,10 +140,8 @@ int attach_reference(mt_set* set, const double* e_ref, const double* w_ref, cons
 int export_neighbors(const mt_set* set, int32_t* i, int32_t* j, int32_t* shift, hipStream_t stream);
 
 // mt_eval.hip
-int decode_params(mt_set* set, const double* x, int P, hipStream_t stream);
-int launch_batched(mt_set* set, const ItemPlan& plan, const LaunchCfg& cfg, int P, int precision,
-                   int mode, const double* vel, double* force, double* atom_virial,
-                   hipStream_t stream);
+int launch_batched(mt_set* set, const LaunchCfg& cfg, int P, int precision, int mode,
+                   const double* vel, double* force, double* atom_virial, hipStream_t stream);
 int launch_plain(mt_set* set, int P, int precision, int mode, const double* vel, double* force,
                  double* atom_virial, hipStream_t stream);
 int launch_large(mt_set* set, int P, int precision, int mode, const double* vel, double* force,
@@ -120,16 +149,25 @@ int launch_large(mt_set* set, int P, int precision, int mode, const double* vel,
 int launch_finalize_fit(mt_set* set, int P, const double* w, double* Z, hipStream_t stream);
 int launch_finalize_eval(mt_set* set, int P, double* energy, double* virial, double* heat,
                          hipStream_t stream);
-int launch_adjoint(mt_set* set, const ItemPlan& plan, const LaunchCfg& cfg, int P, int precision,
-                   const double* w, const double* Z, hipStream_t stream);
+int launch_adjoint(mt_set* set, const LaunchCfg& cfg, int P, int precision, const double* w,
+                   const double* Z, hipStream_t stream);
 int launch_adjoint_plain(mt_set* set, int P, int precision, const double* w, const double* Z,
                          hipStream_t stream);
 int launch_finalize_grad(mt_set* set, int P, const double* Z, double* dZdx, hipStream_t stream);
 
 enum Mode { MODE_FIT = 0, MODE_EVAL = 1 };
 
-ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int precision);
+ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int family);
 LaunchCfg default_cfg(const mt_set* set, int P, int precision);
-size_t lds_bytes(const mt_set* set, int block, int elem);
+int class_of(int family, int kmax);
+const std::vector<int>& family_classes(int family);
+
+// Start/stop events for one kernel launch when the set is profiling (kind 0
+// batched, 1 adjoint); null events otherwise.  The launch records them around
+// the dispatch itself (hipExtLaunchKernelGGL).
+struct ProfScope {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ProfScope(mt_set* s, int kind);
+};
 
 }  // namespace mt

@@ -1,0 +1,629 @@
+// Device code of the evaluation kernels, shared by the per-family translation
+// units (each instantiates the kernels of one precision / mode).
+//
+// Batched kernel.  A work item is (structure s, candidates c0 .. c0+nc-1).  A
+// block of B threads holds R = B / npad_s replicas of the structure (npad_s is
+// the atom count rounded up to 8/16/32/64 or to a multiple of 64), one atom per
+// thread; replica q evaluates candidates c0 + q, c0 + q + R, ...  At the start
+// of an item the block decodes the item's parameter sets into LDS; the bond
+// geometry of the thread's atom is loaded once into registers and reused for
+// every candidate.  Forces need the other atom's bond gradient
+// (F_i = sum_j G_ij - G_ji): every thread writes its bond gradients to its
+// exchange slots in LDS and reads back the reverse bonds.  A replica of up to
+// 64 atoms lives inside one wavefront, whose LDS accesses are ordered, so it
+// needs no barrier; larger replicas synchronise the block.  Per-atom energy,
+// virial and squared force residual are reduced in float64 over aligned lane
+// groups (transpose reduction over DPP / permlane exchanges) and written to one
+// partial-sum slot per (candidate, structure, wavefront); the finalize kernels
+// add the slots in a fixed order, so results are deterministic.
+//
+// Coordination classes.  Atoms inside a structure are sorted by coordination
+// and each wavefront runs the variant compiled for its largest coordination M,
+// so control flow is uniform.  A kernel instance serves one class MC: it holds
+// the variants M = LO..MC (a wavefront with M < LO runs the LO variant with
+// padded bonds), and a structure is routed to the smallest class that covers
+// its largest coordination.  Register allocation then follows the class, so
+// diamond-like structures (M <= 4) run at high occupancy.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "mt_host.h"
+#include "mt_site.h"
+
+namespace mt {
+
+// ---------------------------------------------------------------------------
+// Parameter decode (Sec. II.B): x = [D0, alpha, r0, beta, n, h] with S = 2,
+// so lambda = 2 alpha, mu = alpha, f_R = D0 e^{-2 alpha (r - r0)},
+// f_A = 2 D0 e^{-alpha (r - r0)}.  A candidate outside the potential's domain
+// is replaced by a harmless stand-in so the arithmetic stays finite; its
+// outputs are set to NaN by the finalize kernels.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool params_valid(const double* __restrict__ x) {
+    const double D0 = x[0], al = x[1], r0 = x[2], be = x[3], n = x[4], h = x[5];
+    return isfinite(D0) && isfinite(al) && isfinite(r0) && isfinite(be) && isfinite(n) &&
+           isfinite(h) && D0 > 0.0 && al > 0.0 && n > 0.0 && be >= 0.0;
+}
+
+template <typename S>
+__device__ __forceinline__ void decode_record(const double* __restrict__ x, S* __restrict__ o) {
+    double D0 = x[0], al = x[1], r0 = x[2], be = x[3], n = x[4], h = x[5];
+    const bool ok = params_valid(x);
+    if (!ok) { D0 = 3.0; al = 1.4; r0 = 2.2; be = 0.3; n = 0.6; h = -0.6; }
+    o[P_AL] = (S)(al * 1.4426950408889634);
+    const S r0hi = (S)r0;
+    o[P_R0HI] = r0hi;
+    o[P_R0LO] = (S)(r0 - (double)r0hi);
+    o[P_D0] = (S)D0;
+    o[P_2D0] = (S)(2.0 * D0);
+    o[P_ALPHA] = (S)al;
+    o[P_BETA] = (S)be;
+    o[P_N] = (S)n;
+    o[P_NINV2N] = (S)(-1.0 / (2.0 * n));
+    o[P_H] = (S)h;
+    o[P_VALID] = ok ? S(1) : S(0);
+}
+
+template <typename S>
+struct alignas(4 * sizeof(S)) Vec4 {
+    S x, y, z, w;
+};
+
+template <typename S>
+struct BArgs {
+    SetDev set;
+    const Item* items;
+    const int* bin_off;
+    const double* x;          // [P][6] parameter sets
+    double* partial;          // [P][nslots][nv]
+    int nv;
+    int ptile;                // largest candidate count of an item in this launch
+    // MODE_EVAL outputs (caller numbering); may be null
+    double* force;            // [P][3][N]
+    double* atom_virial;      // [P][9][N]
+    const double* vel;        // [3][N]
+    // adjoint inputs
+    const double* coef;       // [P][S][8]
+};
+
+template <typename S>
+__device__ __forceinline__ GeomArrays<S> geom_of(const SetDev& d);
+template <>
+__device__ __forceinline__ GeomArrays<float> geom_of<float>(const SetDev& d) { return d.gf; }
+template <>
+__device__ __forceinline__ GeomArrays<double> geom_of<double>(const SetDev& d) { return d.gd; }
+template <typename S>
+__device__ __forceinline__ const S* fref_of(const SetDev& d);
+template <>
+__device__ __forceinline__ const float* fref_of<float>(const SetDev& d) { return d.fref32; }
+template <>
+__device__ __forceinline__ const double* fref_of<double>(const SetDev& d) { return d.fref64; }
+
+struct ItemCtx {
+    int s, a0, Ns, npad, R, q, la, atom, steps, slot, g, xsz, own;
+    bool active, block_sync;
+};
+
+__device__ __forceinline__ ItemCtx item_ctx(const SetDev& d, const Item& it) {
+    // Item fields are uniform across the block; npad is 8, 16, 32, 64 or a
+    // multiple of 64, so lane -> (replica, atom) needs no vector division.
+    ItemCtx x;
+    x.s = it.s;
+    x.a0 = d.st_off[x.s];
+    x.Ns = d.st_off[x.s + 1] - x.a0;
+    x.npad = d.st_npad[x.s];
+    const int tid = threadIdx.x;
+    if (x.npad <= 64) {
+        const int sh = 31 - __clz(x.npad);
+        x.R = blockDim.x >> sh;
+        x.q = tid >> sh;
+        x.la = tid & (x.npad - 1);
+        x.g = x.npad;
+    } else {
+        const int wpr = x.npad >> 6;                       // wavefronts per replica
+        const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+        x.R = (blockDim.x >> 6) / wpr;
+        const int qw = wid / wpr;                          // scalar division
+        x.q = qw;
+        x.la = ((wid - qw * wpr) << 6) + (tid & 63);
+        x.g = 64;
+    }
+    x.active = (x.q < x.R) && (x.la < x.Ns);
+    x.atom = x.a0 + (x.active ? x.la : 0);
+    x.steps = (it.nc + x.R - 1) / x.R;
+    x.slot = d.st_slot[x.s] + (x.npad > 64 ? (x.la >> 6) : 0);
+    x.xsz = d.st_xsize[x.s];
+    x.block_sync = x.npad > 64;
+    // own exchange slot base: the chunk's first atom is always a real atom
+    const int first = x.la & ~(x.g - 1);
+    x.own = (x.q < x.R) ? (d.xbase[x.a0 + first] + (x.la - first) + x.q * x.xsz) : 0;
+    return x;
+}
+
+// LDS ordering: a replica inside one wavefront only needs the compiler not to
+// move LDS accesses across this point; larger replicas need the block barrier.
+__device__ __forceinline__ void exchange_sync(bool block) {
+    if (block) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// Store the group sums of v[0..7] into partial[c][slot][off + vidx].
+__device__ __forceinline__ void store_group(double* v, const ItemCtx& x, bool group_ok,
+                                            double* __restrict__ partial, int nslots, int nv,
+                                            int c, int off, int wmask) {
+    int vidx;
+    const double sum = group_reduce8(v, x.g, &vidx);
+    const int lane = threadIdx.x & 63;
+    if (group_ok && (lane & ((x.g >> 3) - 1)) == 0 && ((wmask >> vidx) & 1))
+        partial[((size_t)c * nslots + x.slot) * nv + off + vidx] = sum;
+}
+
+// LDS layout of a block: [ptile x kNParam parameter records][R x xsz exchange
+// slots (Vec4)][adjoint: R x npad force residuals (Vec4)].
+template <typename S>
+__device__ __forceinline__ size_t lds_param_bytes(int ptile) {
+    return ((size_t)ptile * kNParam * sizeof(S) + 31) & ~(size_t)31;
+}
+
+template <typename S, int MODE, int M>
+__device__ __forceinline__ void run_batched(const BArgs<S>& A, const Item& it, const ItemCtx& x,
+                                            unsigned char* __restrict__ lds) {
+    const SetDev& d = A.set;
+    const int N = d.N;
+    const S* __restrict__ pbuf = reinterpret_cast<const S*>(lds);
+    Vec4<S>* __restrict__ xb = reinterpret_cast<Vec4<S>*>(lds + lds_param_bytes<S>(A.ptile));
+    Geo<S, M> g;
+    g.load(geom_of<S>(d), N, x.atom, x.active);
+    constexpr int MM = M > 0 ? M : 1;
+    int rv[MM];
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+        rv[m] = x.active ? d.rev[(size_t)m * N + x.atom] + x.q * x.xsz : x.own + m * x.g;
+    const S* fr = fref_of<S>(d);
+    S frx = S(0), fry = S(0), frz = S(0);
+    if (MODE == MODE_FIT && x.active) {
+        frx = fr[x.atom]; fry = fr[(size_t)N + x.atom]; frz = fr[(size_t)2 * N + x.atom];
+    }
+    const int orig = x.active ? d.perm[x.atom] : 0;
+    S vx = S(0), vy = S(0), vz = S(0);
+    if (MODE == MODE_EVAL && A.vel && x.active) {
+        vx = (S)A.vel[orig]; vy = (S)A.vel[(size_t)N + orig]; vz = (S)A.vel[(size_t)2 * N + orig];
+    }
+
+    for (int step = 0; step < x.steps; ++step) {
+        const int cl = x.q + step * x.R;
+        const bool group_ok = cl < it.nc;
+        const bool cok = x.active && group_ok;
+        const int clv = group_ok ? cl : 0;
+        const int c = it.c0 + clv;
+        Cand<S, S> p;
+        load_cand(pbuf + kNParam * clv, p);
+        S U;
+        S Gx[MM], Gy[MM], Gz[MM];
+        site_eval<S, S, M>(g, p, U, Gx, Gy, Gz);
+#pragma unroll
+        for (int m = 0; m < M; ++m) xb[x.own + m * x.g] = Vec4<S>{Gx[m], Gy[m], Gz[m], S(0)};
+        exchange_sync(x.block_sync);
+        S Fx = S(0), Fy = S(0), Fz = S(0);
+        S wi[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) wi[k] = S(0);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const Vec4<S> r = xb[rv[m]];
+            Fx += Gx[m] - r.x;
+            Fy += Gy[m] - r.y;
+            Fz += Gz[m] - r.z;
+            if (MODE == MODE_EVAL) {
+                const S dx = g.rhi[m] * g.ux[m], dy = g.rhi[m] * g.uy[m], dz = g.rhi[m] * g.uz[m];
+                wi[0] += dx * r.x; wi[1] += dx * r.y; wi[2] += dx * r.z;
+                wi[3] += dy * r.x; wi[4] += dy * r.y; wi[5] += dy * r.z;
+                wi[6] += dz * r.x; wi[7] += dz * r.y; wi[8] += dz * r.z;
+            }
+        }
+        exchange_sync(x.block_sync);
+        S w6[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) w6[k] = S(0);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const S dx = g.rhi[m] * g.ux[m], dy = g.rhi[m] * g.uy[m], dz = g.rhi[m] * g.uz[m];
+            w6[0] -= dx * Gx[m]; w6[1] -= dy * Gy[m]; w6[2] -= dz * Gz[m];
+            w6[3] -= dy * Gz[m]; w6[4] -= dz * Gx[m]; w6[5] -= dx * Gy[m];
+        }
+        // Lanes outside the structure have zero geometry and zero reference
+        // forces, so their energy, virial and residual are exactly zero.
+        double v[8];
+        v[0] = (double)U;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[1 + k] = (double)w6[k];
+        if (MODE == MODE_FIT) {
+            const S ax = Fx - frx, ay = Fy - fry, az = Fz - frz;
+            v[7] = (double)(ax * ax + ay * ay + az * az);
+            store_group(v, x, group_ok, A.partial, d.nslots, A.nv, c, 0, 0xff);
+        } else {
+            v[7] = 0.0;
+            store_group(v, x, group_ok, A.partial, d.nslots, A.nv, c, 0, 0xff);
+            double u[8];
+            const S jx = wi[0] * vx + wi[1] * vy + wi[2] * vz;
+            const S jy = wi[3] * vx + wi[4] * vy + wi[5] * vz;
+            const S jz = wi[6] * vx + wi[7] * vy + wi[8] * vz;
+            u[0] = (double)jx;
+            u[1] = (double)jy;
+            u[2] = (double)jz;
+            u[3] = u[4] = u[5] = u[6] = u[7] = 0.0;
+            store_group(u, x, group_ok, A.partial, d.nslots, A.nv, c, 8, 0x07);
+            if (cok && A.force) {
+                double* f = A.force + (size_t)c * 3 * N;
+                f[orig] = (double)Fx;
+                f[(size_t)N + orig] = (double)Fy;
+                f[(size_t)2 * N + orig] = (double)Fz;
+            }
+            if (cok && A.atom_virial) {
+                double* w = A.atom_virial + (size_t)c * 9 * N;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) w[(size_t)k * N + orig] = (double)wi[k];
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void run_idle(int steps, int barriers) {
+    for (int step = 0; step < steps; ++step)
+        for (int b = 0; b < barriers; ++b) __syncthreads();
+}
+
+// Call f(integral_constant<M>) for the variant that serves coordination m.
+template <int LO, int HI, typename F>
+__device__ __forceinline__ void dispatch_m(int m, F&& f) {
+    if constexpr (LO >= HI) {
+        f(std::integral_constant<int, HI>{});
+    } else {
+        if (m <= LO) f(std::integral_constant<int, LO>{});
+        else dispatch_m<LO + 1, HI>(m, f);
+    }
+}
+
+// Lowest compiled variant of a class; the exchange-slot layout of the set
+// reserves at least this many slots per atom for structures of the class.
+template <int MC>
+struct ClassLo {
+    static constexpr int value = MC <= 4 ? 0 : 3;
+};
+
+// Decode the item's parameter sets into the LDS records (all threads take part).
+template <typename S>
+__device__ __forceinline__ void decode_item(const BArgs<S>& A, const Item& it, unsigned char* lds) {
+    S* pbuf = reinterpret_cast<S*>(lds);
+    for (int t = threadIdx.x; t < it.nc; t += blockDim.x)
+        decode_record<S>(A.x + 6 * (size_t)(it.c0 + t), pbuf + kNParam * t);
+    __syncthreads();
+}
+
+template <typename S, int MODE, int MC>
+__device__ __forceinline__ void batched_item(const BArgs<S>& A, const Item& it, unsigned char* lds) {
+    decode_item<S>(A, it, lds);
+    const ItemCtx x = item_ctx(A.set, it);
+    const int Mi = x.active ? A.set.nnb[x.atom] : -1;
+    const int Mw = wave_max_int(Mi);
+    if (Mw < 0) {
+        // whole wavefront outside every replica: only larger replicas have such
+        // wavefronts, and they synchronise the block twice per step
+        run_idle(x.steps, 2);
+        return;
+    }
+    dispatch_m<ClassLo<MC>::value, MC>(Mw, [&](auto mv) {
+        run_batched<S, MODE, decltype(mv)::value>(A, it, x, lds);
+    });
+}
+
+// Occupancy target per class: the M <= 4 class fits 4 wavefronts per SIMD.
+template <typename S, int MC>
+struct WavesPerEU {
+    static constexpr int value = (MC <= 4 && sizeof(S) == 4) ? 4 : 1;
+};
+
+template <typename S, int MODE, int MC>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S, MC>::value)))
+void k_batched(BArgs<S> A) {
+    extern __shared__ __align__(32) unsigned char lds_raw[];
+    const int b0 = A.bin_off[blockIdx.x], b1 = A.bin_off[blockIdx.x + 1];
+    for (int i = b0; i < b1; ++i) {
+        const Item it = A.items[i];
+        batched_item<S, MODE, MC>(A, it, lds_raw);
+        __syncthreads();
+    }
+}
+
+// The plain schedule: one launch per (candidate, structure), a single block
+// that evaluates the item A.items[0].  The same device code as k_batched,
+// under a kernel name of its own so that profiles keep the two apart.
+template <typename S, int MODE, int MC>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S, MC>::value)))
+void k_plain(BArgs<S> A) {
+    extern __shared__ __align__(32) unsigned char lds_raw[];
+    batched_item<S, MODE, MC>(A, A.items[0], lds_raw);
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint kernel: dZ/dx of the fitness.  For candidate c and structure s,
+//   dZ/dx|_s = sum_i [ k_e U_i' - sum_j G_ij' . delta_ij ],
+//   delta_ij = k_f (a_j - a_i) + C_s r_ij,   a = F - F*,
+// where ' is the derivative with respect to the six parameters (forward-mode
+// dual numbers), k_e = w_e (e_s - e*_s)/(N_s Z_e Q_e), k_f = w_f/(Z_f Q_f) and
+// C_s = w_v/(N_s Z_v Q_v) times the symmetric matrix of virial residuals (off
+// diagonals halved).  These follow from dF_i/dx = -d/dx dE/dr_i and
+// dW/dx = -sum r_ij (x) dG_ij/dx.
+// ---------------------------------------------------------------------------
+template <typename S, int M>
+__device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, const ItemCtx& x,
+                                            unsigned char* __restrict__ lds) {
+    const SetDev& d = A.set;
+    const int N = d.N;
+    const S* __restrict__ pbuf = reinterpret_cast<const S*>(lds);
+    Vec4<S>* __restrict__ xb = reinterpret_cast<Vec4<S>*>(lds + lds_param_bytes<S>(A.ptile));
+    Vec4<S>* __restrict__ ab = xb + (size_t)x.R * x.xsz + (size_t)x.q * x.npad;
+    Geo<S, M> g;
+    g.load(geom_of<S>(d), N, x.atom, x.active);
+    constexpr int MM = M > 0 ? M : 1;
+    int rv[MM], jl[MM];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        rv[m] = x.active ? d.rev[(size_t)m * N + x.atom] + x.q * x.xsz : x.own + m * x.g;
+        jl[m] = x.active ? d.jl[(size_t)m * N + x.atom] : x.la;
+    }
+    const S* fr = fref_of<S>(d);
+    S frx = S(0), fry = S(0), frz = S(0);
+    if (x.active) { frx = fr[x.atom]; fry = fr[(size_t)N + x.atom]; frz = fr[(size_t)2 * N + x.atom]; }
+
+    for (int step = 0; step < x.steps; ++step) {
+        const int cl = x.q + step * x.R;
+        const bool group_ok = cl < it.nc;
+        const bool cok = x.active && group_ok;
+        const int clv = group_ok ? cl : 0;
+        const int c = it.c0 + clv;
+        Cand<Dual<S>, S> p;
+        load_cand(pbuf + kNParam * clv, p);
+        Dual<S> U;
+        Dual<S> Gx[MM], Gy[MM], Gz[MM];
+        site_eval<Dual<S>, S, M>(g, p, U, Gx, Gy, Gz);
+#pragma unroll
+        for (int m = 0; m < M; ++m) xb[x.own + m * x.g] = Vec4<S>{Gx[m].v, Gy[m].v, Gz[m].v, S(0)};
+        exchange_sync(x.block_sync);
+        S ax = S(0), ay = S(0), az = S(0);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const Vec4<S> r = xb[rv[m]];
+            ax += Gx[m].v - r.x;
+            ay += Gy[m].v - r.y;
+            az += Gz[m].v - r.z;
+        }
+        ax -= frx; ay -= fry; az -= frz;
+        ab[x.la] = Vec4<S>{ax, ay, az, S(0)};
+        exchange_sync(x.block_sync);
+        const double* cf = A.coef + ((size_t)c * d.S + x.s) * 8;
+        const S ke = (S)cf[0], kf = (S)cf[1];
+        const S cxx = (S)cf[2], cyy = (S)cf[3], czz = (S)cf[4];
+        const S cyz = (S)cf[5], czx = (S)cf[6], cxy = (S)cf[7];
+        S phi[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) phi[k] = ke * U.d[k];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const Vec4<S> aj = ab[jl[m]];
+            const S dx = g.rhi[m] * g.ux[m], dy = g.rhi[m] * g.uy[m], dz = g.rhi[m] * g.uz[m];
+            const S ex = kf * (aj.x - ax) + cxx * dx + cxy * dy + czx * dz;
+            const S ey = kf * (aj.y - ay) + cxy * dx + cyy * dy + cyz * dz;
+            const S ez = kf * (aj.z - az) + czx * dx + cyz * dy + czz * dz;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) phi[k] -= Gx[m].d[k] * ex + Gy[m].d[k] * ey + Gz[m].d[k] * ez;
+        }
+        exchange_sync(x.block_sync);
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[k] = (double)phi[k];
+        v[6] = v[7] = 0.0;
+        store_group(v, x, group_ok, A.partial, d.nslots, A.nv, c, 0, 0x3f);
+    }
+}
+
+template <typename S, int MC>
+__device__ __forceinline__ void adjoint_item(const BArgs<S>& A, const Item& it, unsigned char* lds) {
+    decode_item<S>(A, it, lds);
+    const ItemCtx x = item_ctx(A.set, it);
+    const int Mi = x.active ? A.set.nnb[x.atom] : -1;
+    const int Mw = wave_max_int(Mi);
+    if (Mw < 0) {
+        run_idle(x.steps, 3);
+        return;
+    }
+    dispatch_m<ClassLo<MC>::value, MC>(Mw, [&](auto mv) {
+        run_adjoint<S, decltype(mv)::value>(A, it, x, lds);
+    });
+}
+
+template <typename S, int MC>
+__global__ __launch_bounds__(512) void k_adjoint(BArgs<S> A) {
+    extern __shared__ __align__(32) unsigned char lds_raw[];
+    const int b0 = A.bin_off[blockIdx.x], b1 = A.bin_off[blockIdx.x + 1];
+    for (int i = b0; i < b1; ++i) {
+        const Item it = A.items[i];
+        adjoint_item<S, MC>(A, it, lds_raw);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Large structures (more atoms than one block holds): two passes per
+// candidate.  Pass 1 writes every bond gradient to global memory and the
+// energy/virial partials; pass 2 gathers forces, per-atom virial, heat
+// current and the force residual.
+// ---------------------------------------------------------------------------
+struct LArgs {
+    int s, c0;                 // structure, first candidate of the chunk
+    void* gbuf;                // [chunk][3][nbs] of S
+};
+
+template <typename S, int M>
+__device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L, int atom, bool active) {
+    const SetDev& d = A.set;
+    const int N = d.N;
+    Geo<S, M> g;
+    g.load(geom_of<S>(d), N, atom, active);
+    constexpr int MM = M > 0 ? M : 1;
+    const int c = L.c0 + blockIdx.y;
+    const int a0 = d.st_off[L.s];
+    const int nbs = d.st_boff[L.s + 1] - d.st_boff[L.s];
+    const int Mi = active ? d.nnb[atom] : 0;
+    const int lb = active ? d.lbo[atom] : 0;
+    S rec[kNParam];
+    decode_record<S>(A.x + 6 * (size_t)c, rec);
+    Cand<S, S> p;
+    load_cand(rec, p);
+    S U;
+    S Gx[MM], Gy[MM], Gz[MM];
+    site_eval<S, S, M>(g, p, U, Gx, Gy, Gz);
+    S* gb = reinterpret_cast<S*>(L.gbuf) + (size_t)blockIdx.y * 3 * nbs;
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            if (m < Mi) {
+                gb[lb + m] = Gx[m];
+                gb[nbs + lb + m] = Gy[m];
+                gb[2 * nbs + lb + m] = Gz[m];
+            }
+    }
+    S w6[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) w6[k] = S(0);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const S dx = g.rhi[m] * g.ux[m], dy = g.rhi[m] * g.uy[m], dz = g.rhi[m] * g.uz[m];
+        w6[0] -= dx * Gx[m]; w6[1] -= dy * Gy[m]; w6[2] -= dz * Gz[m];
+        w6[3] -= dy * Gz[m]; w6[4] -= dz * Gx[m]; w6[5] -= dx * Gy[m];
+    }
+    double v[8];
+    v[0] = active ? (double)U : 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[1 + k] = active ? (double)w6[k] : 0.0;
+    v[7] = 0.0;
+    int vidx;
+    const double sum = group_reduce8(v, 64, &vidx);
+    const int lane = threadIdx.x & 63;
+    const int slot = d.st_slot[L.s] + ((atom - a0) >> 6);
+    if ((lane & 7) == 0 && vidx < 7)
+        A.partial[((size_t)c * d.nslots + slot) * A.nv + vidx] = sum;
+}
+
+template <typename S, int MC>
+__global__ __launch_bounds__(256) void k_large_site(BArgs<S> A, LArgs L) {
+    const SetDev& d = A.set;
+    const int a0 = d.st_off[L.s], Ns = d.st_off[L.s + 1] - a0;
+    const int la = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = la < Ns;
+    const int atom = a0 + (active ? la : 0);
+    const int Mi = active ? d.nnb[atom] : -1;
+    const int Mw = wave_max_int(Mi);
+    if (Mw < 0) return;
+    dispatch_m<ClassLo<MC>::value, MC>(Mw, [&](auto mv) {
+        run_large_site<S, decltype(mv)::value>(A, L, atom, active);
+    });
+}
+
+template <typename S, int MODE>
+__global__ __launch_bounds__(256) void k_large_gather(BArgs<S> A, LArgs L) {
+    const SetDev& d = A.set;
+    const int N = d.N;
+    const int a0 = d.st_off[L.s], Ns = d.st_off[L.s + 1] - a0;
+    const int nbs = d.st_boff[L.s + 1] - d.st_boff[L.s];
+    const int la = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = la < Ns;
+    const int atom = a0 + (active ? la : 0);
+    const int c = L.c0 + blockIdx.y;
+    const S* gb = reinterpret_cast<const S*>(L.gbuf) + (size_t)blockIdx.y * 3 * nbs;
+    const GeomArrays<S> G = geom_of<S>(d);
+    S Fx = S(0), Fy = S(0), Fz = S(0);
+    S wi[9];
+    for (int k = 0; k < 9; ++k) wi[k] = S(0);
+    if (active) {
+        const int Mi = d.nnb[atom], lb = d.lbo[atom];
+        for (int m = 0; m < Mi; ++m) {
+            const size_t o = (size_t)m * N + atom;
+            const int r = d.revc[o];
+            const S rx = gb[r], ry = gb[nbs + r], rz = gb[2 * nbs + r];
+            Fx += gb[lb + m] - rx;
+            Fy += gb[nbs + lb + m] - ry;
+            Fz += gb[2 * nbs + lb + m] - rz;
+            if (MODE == MODE_EVAL) {
+                const S rr = G.rhi[o];
+                const S dx = rr * G.ux[o], dy = rr * G.uy[o], dz = rr * G.uz[o];
+                wi[0] += dx * rx; wi[1] += dx * ry; wi[2] += dx * rz;
+                wi[3] += dy * rx; wi[4] += dy * ry; wi[5] += dy * rz;
+                wi[6] += dz * rx; wi[7] += dz * ry; wi[8] += dz * rz;
+            }
+        }
+    }
+    const int orig = active ? d.perm[atom] : 0;
+    double v[8];
+    for (int k = 0; k < 8; ++k) v[k] = 0.0;
+    const int lane = threadIdx.x & 63;
+    const int slot = d.st_slot[L.s] + (la >> 6);
+    int vidx;
+    if (MODE == MODE_FIT) {
+        const S* fr = fref_of<S>(d);
+        if (active) {
+            const S ax = Fx - fr[atom], ay = Fy - fr[(size_t)N + atom], az = Fz - fr[(size_t)2 * N + atom];
+            v[7] = (double)(ax * ax + ay * ay + az * az);
+        }
+        const double sum = group_reduce8(v, 64, &vidx);
+        if ((lane & 7) == 0 && vidx == 7) A.partial[((size_t)c * d.nslots + slot) * A.nv + 7] = sum;
+    } else {
+        if (active && A.vel) {
+            const S vx = (S)A.vel[orig], vy = (S)A.vel[(size_t)N + orig], vz = (S)A.vel[(size_t)2 * N + orig];
+            v[0] = (double)(wi[0] * vx + wi[1] * vy + wi[2] * vz);
+            v[1] = (double)(wi[3] * vx + wi[4] * vy + wi[5] * vz);
+            v[2] = (double)(wi[6] * vx + wi[7] * vy + wi[8] * vz);
+        }
+        const double sum = group_reduce8(v, 64, &vidx);
+        if ((lane & 7) == 0 && vidx < 3) A.partial[((size_t)c * d.nslots + slot) * A.nv + 8 + vidx] = sum;
+        if (active && A.force) {
+            double* f = A.force + (size_t)c * 3 * N;
+            f[orig] = (double)Fx; f[(size_t)N + orig] = (double)Fy; f[(size_t)2 * N + orig] = (double)Fz;
+        }
+        if (active && A.atom_virial) {
+            double* w = A.atom_virial + (size_t)c * 9 * N;
+            for (int k = 0; k < 9; ++k) w[(size_t)k * N + orig] = (double)wi[k];
+        }
+    }
+}
+
+// Launchers, one per kernel family (defined in the mt_k_*.hip units).
+hipError_t launch_fit32(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<float>& A,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_eval32(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<float>& A,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_fit64(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<double>& A,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_eval64(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<double>& A,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_adj32(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<float>& A,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_adj64(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<double>& A,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// Plain-schedule launchers (one block, one item); mode is MODE_FIT or MODE_EVAL.
+hipError_t launch_plain32(int mode, int mc, dim3 b, size_t lds, hipStream_t st, const BArgs<float>& A);
+hipError_t launch_plain64(int mode, int mc, dim3 b, size_t lds, hipStream_t st, const BArgs<double>& A);
+hipError_t launch_large32(int mc, int mode, dim3 g, dim3 b, hipStream_t st, const BArgs<float>& A,
+                          const LArgs& L);
+hipError_t launch_large64(int mc, int mode, dim3 g, dim3 b, hipStream_t st, const BArgs<double>& A,
+                          const LArgs& L);
+
+}  // namespace mt

@@ -265,9 +265,11 @@ __global__ void k_sort_by_coordination(const int* __restrict__ st_off, int kcap,
 // Per structure (one block each): coordination in sorted order, local bond
 // offsets, bonds, largest coordination and ordered triplets.
 __global__ void k_struct_tables(const int* __restrict__ st_off, const int* __restrict__ perm,
-                                const int* __restrict__ cnt, int* __restrict__ nnb,
-                                int* __restrict__ lbo, int* __restrict__ st_nbonds,
-                                int* __restrict__ st_kmax, long long* __restrict__ st_trip) {
+                                const int* __restrict__ cnt, const int* __restrict__ st_npad,
+                                int* __restrict__ nnb, int* __restrict__ lbo,
+                                int* __restrict__ st_nbonds, int* __restrict__ st_kmax,
+                                long long* __restrict__ st_trip, int* __restrict__ xbase,
+                                int* __restrict__ st_xsize) {
     __shared__ int sh[16];
     __shared__ int kmax_sh;
     __shared__ unsigned long long trip_sh;
@@ -295,6 +297,32 @@ __global__ void k_struct_tables(const int* __restrict__ st_off, const int* __res
         st_kmax[s] = kmax_sh;
         st_trip[s] = (long long)trip_sh;
     }
+    // Exchange slots of the batched kernels (structures up to kMaxBatched atoms):
+    // chunks of G lanes, chunk c holds K_c * G slots.
+    __shared__ int choff[kMaxBatched / 8 + 1];
+    const int npad = st_npad[s];
+    const int ns = a1 - a0;
+    if (npad > 0) {
+        const int G = npad < 64 ? npad : 64;
+        const int nch = npad / G;
+        const int lo = kmax_sh <= 4 ? 0 : 3;     // lowest variant of the structure's class
+        if (threadIdx.x == 0) {
+            int off = 0;
+            for (int c = 0; c < nch; ++c) {
+                int K = lo;
+                for (int l = c * G; l < (c + 1) * G && l < ns; ++l) K = max(K, nnb[a0 + l]);
+                choff[c] = off;
+                off += K * G;
+            }
+            choff[nch] = off;
+            st_xsize[s] = off;
+        }
+        __syncthreads();
+        for (int l = threadIdx.x; l < ns; l += blockDim.x) xbase[a0 + l] = choff[l / G] + (l % G);
+    } else {
+        for (int l = threadIdx.x; l < ns; l += blockDim.x) xbase[a0 + l] = 0;
+        if (threadIdx.x == 0) st_xsize[s] = 0;
+    }
 }
 
 // Bond geometry for every (sorted atom, slot).  Padded slots (m >= coordination)
@@ -304,9 +332,11 @@ __global__ void k_geometry(int N, int S, int kcap, double R1, double R2,
                            const StructMeta* __restrict__ meta, const int* __restrict__ perm,
                            const int* __restrict__ inv, const int* __restrict__ cnt,
                            const int* __restrict__ ent_j, const int* __restrict__ ent_sh,
-                           const int* __restrict__ lbo,
-                           float* __restrict__ gf, float* __restrict__ gf_rlo, double* __restrict__ gd,
-                           int* __restrict__ rev, int* __restrict__ jl,
+                           const int* __restrict__ lbo, const int* __restrict__ xbase,
+                           const int* __restrict__ st_npad,
+                           float* __restrict__ gf, float* __restrict__ gf_rlo, float4* __restrict__ gpk,
+                           double* __restrict__ gd,
+                           int* __restrict__ rev, int* __restrict__ revc, int* __restrict__ jl,
                            int* __restrict__ nbr_j, int* __restrict__ nbr_sh, int* __restrict__ flags) {
     int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= N * kcap) return;
@@ -322,15 +352,23 @@ __global__ void k_geometry(int N, int S, int kcap, double R1, double R2,
     double* d_ux = gd;        double* d_uy = gd + KN;   double* d_uz = gd + 2 * KN;
     double* d_r = gd + 3 * KN;  double* d_rinv = gd + 4 * KN;
     double* d_fc = gd + 5 * KN; double* d_fcp = gd + 6 * KN;
+    const int s = struct_of(st_off, S, a);
+    const int npad = st_npad[s];
+    const int G = npad < 64 ? npad : 64;
     if (m >= M) {
         f_ux[o] = f_uy[o] = f_uz[o] = 0.f; f_rhi[o] = 3.0f; gf_rlo[o] = 0.f;
         f_rinv[o] = 0.f; f_fc[o] = 0.f; f_fcp[o] = 0.f;
         d_ux[o] = d_uy[o] = d_uz[o] = 0.0; d_r[o] = 3.0; d_rinv[o] = 0.0;
         d_fc[o] = 0.0; d_fcp[o] = 0.0;
-        rev[o] = -1; jl[o] = -1; nbr_j[o] = -1; nbr_sh[o] = 0;
+        // a padded bond reads back its own (zero) slot and its own atom
+        gpk[o] = make_float4(0.f, 0.f, 0.f, 3.0f);
+        gpk[KN + o] = make_float4(0.f, 0.f, 0.f, 0.f);
+        rev[o] = npad > 0 ? xbase[a] + m * G : 0;
+        revc[o] = 0;
+        jl[o] = a - st_off[s];
+        nbr_j[o] = -1; nbr_sh[o] = 0;
         return;
     }
-    const int s = struct_of(st_off, S, a);
     const StructMeta& me = meta[s];
     const int j = ent_j[m * N + i];
     const int shp = ent_sh[m * N + i];
@@ -357,6 +395,8 @@ __global__ void k_geometry(int N, int S, int kcap, double R1, double R2,
     f_ux[o] = (float)ux; f_uy[o] = (float)uy; f_uz[o] = (float)uz;
     f_rhi[o] = rhi; gf_rlo[o] = (float)(r - (double)rhi);
     f_rinv[o] = (float)rinv; f_fc[o] = (float)fc; f_fcp[o] = (float)fcp;
+    gpk[o] = make_float4((float)ux, (float)uy, (float)uz, rhi);
+    gpk[KN + o] = make_float4((float)(r - (double)rhi), (float)rinv, (float)fc, (float)fcp);
     // reverse entry: (j -> i, -shift) in j's sorted list
     const int want = pack_shift(-n1, -n2, -n3);
     const int Mj = cnt[j];
@@ -365,7 +405,9 @@ __global__ void k_geometry(int N, int S, int kcap, double R1, double R2,
         if (ent_j[q * N + j] == i && ent_sh[q * N + j] == want) { mr = q; break; }
     if (mr < 0) atomicOr(flags, 8);
     const int js = inv[j];
-    rev[o] = mr < 0 ? 0 : lbo[js] + mr;
+    if (mr < 0) mr = 0;
+    rev[o] = npad > 0 ? xbase[js] + mr * G : 0;
+    revc[o] = lbo[js] + mr;
     jl[o] = js - st_off[s];
     nbr_j[o] = j;
     nbr_sh[o] = shp;
@@ -511,6 +553,23 @@ int build_set(mt_set* set, const int64_t* atom_offset, const double* pos, const 
         return MT_ENBR_OVERFLOW;
     }
 
+    // padded sizes depend on atom counts only
+    set->h_npad.assign(S, 0);
+    set->h_large.assign(S, 0);
+    for (int s = 0; s < S; ++s) {
+        const int ns = set->h_off[s + 1] - set->h_off[s];
+        int npad;
+        if (ns <= 8) npad = 8;
+        else if (ns <= 16) npad = 16;
+        else if (ns <= 32) npad = 32;
+        else npad = ((ns + 63) / 64) * 64;
+        const bool large = ns > kMaxBatched;
+        set->h_large[s] = large ? 1 : 0;
+        set->h_npad[s] = large ? 0 : npad;
+    }
+    HIPCHECK(set->st_npad.reserve(sizeof(int) * S));
+    HIPCHECK(hipMemcpyAsync(set->st_npad.p, set->h_npad.data(), sizeof(int) * S, hipMemcpyHostToDevice, st));
+
     HIPCHECK(set->perm.reserve(sizeof(int) * N));
     HIPCHECK(inv.reserve(sizeof(int) * N));
     k_sort_by_coordination<<<S, 256, 0, st>>>(set->st_off.as<int>(), kcap, cnt.as<int>(),
@@ -521,9 +580,12 @@ int build_set(mt_set* set, const int64_t* atom_offset, const double* pos, const 
     HIPCHECK(st_nb.reserve(sizeof(int) * S));
     HIPCHECK(set->st_kmax.reserve(sizeof(int) * S));
     HIPCHECK(st_trip.reserve(sizeof(long long) * S));
+    HIPCHECK(set->xbase.reserve(sizeof(int) * N));
+    HIPCHECK(set->st_xsize.reserve(sizeof(int) * S));
     k_struct_tables<<<S, 256, 0, st>>>(set->st_off.as<int>(), set->perm.as<int>(), cnt.as<int>(),
-                                        set->nnb.as<int>(), set->lbo.as<int>(), st_nb.as<int>(),
-                                        set->st_kmax.as<int>(), st_trip.as<long long>());
+                                        set->st_npad.as<int>(), set->nnb.as<int>(), set->lbo.as<int>(),
+                                        st_nb.as<int>(), set->st_kmax.as<int>(), st_trip.as<long long>(),
+                                        set->xbase.as<int>(), set->st_xsize.as<int>());
     HIPCHECK(hipGetLastError());
     std::vector<int> hnb(S);
     set->h_kmax.assign(S, 0);
@@ -531,13 +593,13 @@ int build_set(mt_set* set, const int64_t* atom_offset, const double* pos, const 
     HIPCHECK(hipMemcpyAsync(hnb.data(), st_nb.p, sizeof(int) * S, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipMemcpyAsync(set->h_kmax.data(), set->st_kmax.p, sizeof(int) * S, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipMemcpyAsync(set->h_trip.data(), st_trip.p, sizeof(long long) * S, hipMemcpyDeviceToHost, st));
+    set->h_xsize.assign(S, 0);
+    HIPCHECK(hipMemcpyAsync(set->h_xsize.data(), set->st_xsize.p, sizeof(int) * S, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
 
     // per-structure launch tables
     set->h_boff.assign(S + 1, 0);
-    set->h_npad.assign(S, 0);
     set->h_slot.assign(S + 1, 0);
-    set->h_large.assign(S, 0);
     set->kmax = 0;
     set->ntrip = 0;
     set->max_atoms = 0;
@@ -548,14 +610,8 @@ int build_set(mt_set* set, const int64_t* atom_offset, const double* pos, const 
         set->kmax = std::max(set->kmax, set->h_kmax[s]);
         set->ntrip += set->h_trip[s];
         set->max_atoms = std::max(set->max_atoms, ns);
-        int npad;
-        if (ns <= 8) npad = 8;
-        else if (ns <= 16) npad = 16;
-        else if (ns <= 32) npad = 32;
-        else npad = ((ns + 63) / 64) * 64;
-        const bool large = ns > kMaxBatched;
-        set->h_large[s] = large ? 1 : 0;
-        set->h_npad[s] = large ? 0 : npad;
+        const bool large = set->h_large[s] != 0;
+        const int npad = set->h_npad[s];
         const int nsl = large ? (ns + 63) / 64 : std::max(1, npad / 64);
         set->h_slot[s + 1] = set->h_slot[s] + nsl;
         if (large) ++set->n_large; else ++set->n_batched;
@@ -563,17 +619,17 @@ int build_set(mt_set* set, const int64_t* atom_offset, const double* pos, const 
     set->nb = set->h_boff[S];
     set->nslots = set->h_slot[S];
     HIPCHECK(set->st_boff.reserve(sizeof(int) * (S + 1)));
-    HIPCHECK(set->st_npad.reserve(sizeof(int) * S));
     HIPCHECK(set->st_slot.reserve(sizeof(int) * (S + 1)));
     HIPCHECK(hipMemcpyAsync(set->st_boff.p, set->h_boff.data(), sizeof(int) * (S + 1), hipMemcpyHostToDevice, st));
-    HIPCHECK(hipMemcpyAsync(set->st_npad.p, set->h_npad.data(), sizeof(int) * S, hipMemcpyHostToDevice, st));
     HIPCHECK(hipMemcpyAsync(set->st_slot.p, set->h_slot.data(), sizeof(int) * (S + 1), hipMemcpyHostToDevice, st));
 
     const size_t KN = (size_t)kcap * N;
     HIPCHECK(set->gf.reserve(sizeof(float) * 7 * KN));
     HIPCHECK(set->gf_rlo.reserve(sizeof(float) * KN));
+    HIPCHECK(set->gpk.reserve(sizeof(float4) * 2 * KN));
     HIPCHECK(set->gd.reserve(sizeof(double) * 7 * KN));
     HIPCHECK(set->rev.reserve(sizeof(int) * KN));
+    HIPCHECK(set->revc.reserve(sizeof(int) * KN));
     HIPCHECK(set->jl.reserve(sizeof(int) * KN));
     HIPCHECK(set->nbr_j.reserve(sizeof(int) * KN));
     HIPCHECK(set->nbr_sh.reserve(sizeof(int) * KN));
@@ -581,8 +637,9 @@ int build_set(mt_set* set, const int64_t* atom_offset, const double* pos, const 
     k_geometry<<<grid_of((long long)KN, 256), 256, 0, st>>>(
         N, S, kcap, set->R1, set->R2, set->st_off.as<int>(), set->pos.as<double>(),
         meta.as<StructMeta>(), set->perm.as<int>(), inv.as<int>(), cnt.as<int>(), ent_j.as<int>(),
-        ent_sh.as<int>(), set->lbo.as<int>(), set->gf.as<float>(), set->gf_rlo.as<float>(),
-        set->gd.as<double>(), set->rev.as<int>(), set->jl.as<int>(), set->nbr_j.as<int>(),
+        ent_sh.as<int>(), set->lbo.as<int>(), set->xbase.as<int>(), set->st_npad.as<int>(),
+        set->gf.as<float>(), set->gf_rlo.as<float>(), set->gpk.as<float4>(),
+        set->gd.as<double>(), set->rev.as<int>(), set->revc.as<int>(), set->jl.as<int>(), set->nbr_j.as<int>(),
         set->nbr_sh.as<int>(), flags.as<int>());
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipMemcpyAsync(&hflags, flags.p, sizeof(int), hipMemcpyDeviceToHost, st));

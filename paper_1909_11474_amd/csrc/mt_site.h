@@ -46,6 +46,20 @@ struct Geo {
     }
 
     __device__ __forceinline__ void load(const GeomArrays<S>& G, int N, int atom, bool active) {
+        if constexpr (sizeof(S) == 4) {
+            if (G.pk0) {
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    const size_t o = (size_t)m * N + atom;
+                    const float4 a = active ? G.pk0[o] : make_float4(0.f, 0.f, 0.f, 3.f);
+                    const float4 b = active ? G.pk1[o] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    ux[m] = a.x; uy[m] = a.y; uz[m] = a.z; rhi[m] = a.w;
+                    rlo[m] = b.x; rinv[m] = b.y; fc[m] = b.z; fcp[m] = b.w;
+                }
+                cache_cos();
+                return;
+            }
+        }
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const size_t o = (size_t)m * N + atom;
@@ -58,6 +72,10 @@ struct Geo {
             fc[m] = active ? G.fc[o] : S(0);
             fcp[m] = active ? G.fcp[o] : S(0);
         }
+        cache_cos();
+    }
+
+    __device__ __forceinline__ void cache_cos() {
         if constexpr (kCache && NP > 0) {
             int p = 0;
 #pragma unroll
@@ -178,46 +196,86 @@ __device__ __forceinline__ void site_eval(const Geo<S, M>& g, const Cand<V, S>& 
     }
 }
 
-// Segmented transpose-reduction of 8 doubles over aligned groups of g lanes
-// (g a power of two, 8 <= g <= 64).  Afterwards every lane holds the group sum
-// of value index *vidx; lanes with (lane & (g/8 - 1)) == 0 are the writers.
-__device__ __forceinline__ double group_reduce8(double* v, int g, int* vidx) {
+// Cross-lane exchanges of a double, 32 bits at a time.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane l <-> 7 - l within 8 (opposite bit 2)
+constexpr int kDppMirror = 0x140;      // lane l <-> 15 - l within 16 (opposite bit 3)
+
+// Transpose step over lane bit m: lanes with the bit clear keep a (and add the
+// partner's a), lanes with it set keep b.  permlane{16,32}_swap exchange the
+// upper half of the first operand with the lower half of the second, so the
+// two returned halves always sum to own kept value + partner's kept value.
+template <int M>
+__device__ __forceinline__ double tstep(double a, double b) {
+    if constexpr (M == 32 || M == 16) {
+        const long long ia = __double_as_longlong(a), ib = __double_as_longlong(b);
+        const unsigned alo = (unsigned)ia, ahi = (unsigned)(ia >> 32);
+        const unsigned blo = (unsigned)ib, bhi = (unsigned)(ib >> 32);
+        unsigned r0lo, r1lo, r0hi, r1hi;
+        if constexpr (M == 32) {
+            auto l = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+            auto h = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+            r0lo = l[0]; r1lo = l[1]; r0hi = h[0]; r1hi = h[1];
+        } else {
+            auto l = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+            auto h = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+            r0lo = l[0]; r1lo = l[1]; r0hi = h[0]; r1hi = h[1];
+        }
+        const double x0 = __longlong_as_double(((long long)r0hi << 32) | r0lo);
+        const double x1 = __longlong_as_double(((long long)r1hi << 32) | r1lo);
+        return x0 + x1;
+    } else {
+        const bool h = (threadIdx.x & M) != 0;
+        const double send = h ? a : b;
+        const double keep = h ? b : a;
+        constexpr int ctrl = M == 8 ? kDppMirror : (M == 4 ? kDppHalfMirror : (M == 2 ? kDppXor2 : kDppXor1));
+        return keep + dpp_mov<ctrl>(send);
+    }
+}
+
+template <int M>
+__device__ __forceinline__ double bstep(double v) {
+    constexpr int ctrl = M == 4 ? kDppHalfMirror : (M == 2 ? kDppXor2 : kDppXor1);
+    return v + dpp_mov<ctrl>(v);
+}
+
+// Segmented transpose-reduction of 8 doubles over aligned groups of G lanes
+// (G in 8, 16, 32, 64): three transpose steps over the top lane bits of the
+// group, then butterfly steps over the rest.  Afterwards every lane holds the
+// group sum of value index *vidx (bits of the transpose steps); lanes with
+// (lane & (G/8 - 1)) == 0 are the writers.
+template <int G>
+__device__ __forceinline__ double group_reduce8_t(double* v, int* vidx) {
+    constexpr int m1 = G / 2, m2 = G / 4, m3 = G / 8;
     const int lane = threadIdx.x & 63;
-    int base = 0;
-    int m = g >> 1;
-    {   // 8 -> 4
-        const int h = (lane & m) ? 1 : 0;
+    double a4[4], a2[2];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const double send = h ? v[k] : v[k + 4];
-            const double keep = h ? v[k + 4] : v[k];
-            v[k] = keep + __shfl_xor(send, m, 64);
-        }
-        base += 4 * h;
-        m >>= 1;
-    }
-    {   // 4 -> 2
-        const int h = (lane & m) ? 1 : 0;
+    for (int k = 0; k < 4; ++k) a4[k] = tstep<m1>(v[k], v[k + 4]);
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const double send = h ? v[k] : v[k + 2];
-            const double keep = h ? v[k + 2] : v[k];
-            v[k] = keep + __shfl_xor(send, m, 64);
-        }
-        base += 2 * h;
-        m >>= 1;
+    for (int k = 0; k < 2; ++k) a2[k] = tstep<m2>(a4[k], a4[k + 2]);
+    double r = tstep<m3>(a2[0], a2[1]);
+    if constexpr (m3 > 4) r = bstep<4>(r);
+    if constexpr (m3 > 2) r = bstep<2>(r);
+    if constexpr (m3 > 1) r = bstep<1>(r);
+    *vidx = ((lane & m1) ? 4 : 0) + ((lane & m2) ? 2 : 0) + ((lane & m3) ? 1 : 0);
+    return r;
+}
+
+__device__ __forceinline__ double group_reduce8(double* v, int g, int* vidx) {
+    switch (g) {
+        case 8: return group_reduce8_t<8>(v, vidx);
+        case 16: return group_reduce8_t<16>(v, vidx);
+        case 32: return group_reduce8_t<32>(v, vidx);
+        default: return group_reduce8_t<64>(v, vidx);
     }
-    {   // 2 -> 1
-        const int h = (lane & m) ? 1 : 0;
-        const double send = h ? v[0] : v[1];
-        const double keep = h ? v[1] : v[0];
-        v[0] = keep + __shfl_xor(send, m, 64);
-        base += h;
-        m >>= 1;
-    }
-    for (; m > 0; m >>= 1) v[0] += __shfl_xor(v[0], m, 64);
-    *vidx = base;
-    return v[0];
 }
 
 __device__ __forceinline__ int wave_max_int(int v) {

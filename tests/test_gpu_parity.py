@@ -186,3 +186,57 @@ def test_error_paths(api):
         ts.fitness(np.array([W.TABLE2_X]))
     assert e.value.code == L.MT_ENOREF
     ts.close()
+
+
+def _force_cfg(ts, P, precision, cache, block, tile, persistent):
+    st = ts.stats()
+    prec = 0 if precision == "fp64" else 1
+    key = (f"N={st['n_atoms']} S={st['n_struct']} nb={st['n_bonds']} trip={st['n_triplets']} "
+           f"P={P} prec={prec}")
+    cache.write_text(f"{key} | block={block} tile={tile} persistent={persistent} ms=0\n")
+    ts.autotune(P, precision, str(cache))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_launch_shapes_give_identical_fitness(api, tmp_path, precision):
+    """Block size, candidate tile and persistent bins change only the schedule:
+    the reduction order is fixed, so Z is bit-identical across launch shapes
+    (and to the plain path)."""
+    wl, refs = small_training(12)
+    ts = api.from_structures(wl.structs)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    X = wl.population
+    P = X.shape[0]
+    ref = ts.fitness(X, precision=precision, schedule="plain").cpu().numpy()
+    k = 0
+    for block in (64, 256, 512):
+        for tile in (1, 8, 32):
+            for persistent in (0, 1):
+                k += 1
+                _force_cfg(ts, P, precision, tmp_path / f"c{k}.txt", block, tile, persistent)
+                Z = ts.fitness(X, precision=precision).cpu().numpy()
+                assert np.array_equal(Z, ref), (block, tile, persistent)
+    ts.close()
+
+
+def test_repeated_graph_replays_are_identical(api):
+    """Graph replays of the same generation give the same Z every time, and a
+    replay picks up new parameter values written into the bound buffer."""
+    import torch
+    wl, refs = small_training(8)
+    ts = api.from_structures(wl.structs)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    X = torch.tensor(wl.population, dtype=torch.float64, device="cuda")
+    Z = torch.empty(X.shape[0], 4, dtype=torch.float64, device="cuda")
+    call = ts.fitness_call(X, Z, precision="fp32")
+    first = call().clone()
+    for _ in range(20):
+        call()
+        torch.cuda.synchronize()
+        assert torch.equal(Z, first)
+    X2 = X.clone()
+    X2[:, 3] *= 1.1                      # new parameters, same buffers
+    X.copy_(X2)
+    changed = call().clone()
+    assert not torch.equal(changed, first)
+    ts.close()

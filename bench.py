@@ -185,16 +185,19 @@ def main():
         refs = {"e": e_ref.cpu().numpy(), "w": w_ref.cpu().numpy(), "f": f_ref.cpu().numpy()}
         top = T.topology(s, wl.R2)
         T.fitness(s, wl.population[:1], refs, topology=top)           # warm-up
+        # candidates in population order, wrapping round, until the budget is spent
         done = 0
         c0 = time.perf_counter()
-        while done < P and time.perf_counter() - c0 < args.cpu_seconds:
-            T.fitness(s, wl.population[done:done + 1], refs, topology=top)
+        while done == 0 or time.perf_counter() - c0 < args.cpu_seconds:
+            k = done % P
+            T.fitness(s, wl.population[k:k + 1], refs, topology=top)
             done += 1
         tc = time.perf_counter() - c0
         cpu = {"value": done * s.n_atoms / tc, "unit": "atom*candidate evals/s",
                "cores": int(_t.get_num_threads()), "kind": "oracle",
-               "sample": f"{done} of {P} candidates x all {s.n_struct} structures "
-                         f"({done * s.n_atoms} atom*candidate evals) in {tc:.1f} s, float64 autograd"}
+               "sample": f"{done} candidate evaluations (population of {P}, in order, wrapping) x "
+                         f"all {s.n_struct} structures = {done * s.n_atoms} atom*candidate evals "
+                         f"in {tc:.1f} s, float64 autograd"}
         log(f"cpu oracle: {cpu['value']:.4e} atom*cand/s on {cpu['cores']} threads")
 
     line = {

@@ -4,19 +4,23 @@
 A step is one GA generation's fitness evaluation: decode the population's
 parameters, evaluate energy, forces and virial of every candidate on every
 training structure, and reduce the weighted energy/virial/force relative-RMSE
-fitness (Sec. III.B of the paper), all in one captured HIP graph.  The
-neighbour lists and bond geometry are built once per structure set (the
-cutoffs are fixed, not fitted) and are not part of a step.
+fitness (Sec. III.B of the paper).  The neighbour lists and bond geometry are
+built once per structure set (the cutoffs are fixed, not fitted) and are not
+part of a step.
 
-Workload (default): 200 candidates x 100 strained 64-atom diamond Si cells,
-float32 arithmetic with float64 accumulation; references from a hidden
-parameter set.  Prints one JSON line on stdout; progress goes to stderr.
+Headline workload: 200 candidates x 100 strained 64-atom diamond Si cells,
+float32 arithmetic with float64 accumulation; reference data from a hidden
+parameter set evaluated by the library's float64 path.  The same run also
+measures the plain schedule (one launch per candidate and structure), the
+fitness gradient, uneven batching (500 candidates x 300 structures of 8-512
+atoms), the gradient over those structures (64 candidates) and the
+64,000-atom force call, and times the CPU oracle on a bounded sample.  Prints
+one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -48,9 +52,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3"])
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--grad-steps", type=int, default=10)
+    ap.add_argument("--uneven-steps", type=int, default=10,
+                    help="generations of the uneven-batching workload (0: skip)")
+    ap.add_argument("--uneven-grad-steps", type=int, default=5,
+                    help="gradient calls over the uneven structures (0: skip)")
+    ap.add_argument("--md-steps", type=int, default=20,
+                    help="64,000-atom force calls (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-time budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -58,6 +67,162 @@ def parse():
     ap.add_argument("--tune-cache", default=TUNED_SHAPES,
                     help="autotune cache file: reuse a stored launch shape, or tune and append one")
     return ap.parse_args()
+
+
+class Timer:
+    """HIP events on the current stream around a region."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.e0 = torch.cuda.Event(enable_timing=True)
+        self.e1 = torch.cuda.Event(enable_timing=True)
+
+    def __enter__(self):
+        self.torch.cuda.synchronize()
+        self.w0 = time.perf_counter()
+        self.e0.record()
+        return self
+
+    def __exit__(self, *exc):
+        self.e1.record()
+        self.enqueue = time.perf_counter() - self.w0
+        self.torch.cuda.synchronize()
+        self.wall = time.perf_counter() - self.w0
+        self.seconds = self.e0.elapsed_time(self.e1) / 1e3
+
+
+def make_set(api, torch, wl):
+    """Set + float64 reference data of the hidden parameter set (per-atom energies
+    and virials, forces), all resident in HBM."""
+    t0 = time.perf_counter()
+    ts = api.from_structures(wl.structs, R1=wl.R1, R2=wl.R2)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    ref = ts.tersoff_eval(wl.hidden_x[None], precision="fp64", forces=True, virial=True)
+    n = torch.as_tensor(wl.structs.sizes().astype(np.float64), device=ref["E"].device)
+    refs = (ref["E"][0] / n, ref["W"][0] / n[:, None], ref["F"][0])
+    ts.attach_reference(*refs)
+    return ts, refs, t_create
+
+
+def set_flops(ts, n_atoms):
+    i, _, _ = ts.neighbors()
+    M = np.bincount(i, minlength=n_atoms)
+    return float(flops_per_atom(M).sum()), float(6 * M.sum())
+
+
+def time_generations(torch, ts, X, Z, steps, warmup):
+    """GPU time of `steps` back-to-back fitness_eval calls (graph replay or direct,
+    as tuned), then the batched kernels' own time from events around each launch."""
+    call = ts.fitness_call(X, Z, precision="fp32", schedule="batched")
+    for _ in range(warmup):
+        call()
+    with Timer(torch) as t:
+        for _ in range(steps):
+            call()
+    ts.profile(True)
+    ts.profile_read()
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    prof = ts.profile_read()["batched"]
+    ts.profile(False)
+    return t, prof
+
+
+def time_plain(torch, ts, X, Z, steps):
+    ts.fitness(X, precision="fp32", schedule="plain", out=Z)
+    with Timer(torch) as t:
+        for _ in range(steps):
+            ts.fitness(X, precision="fp32", schedule="plain", out=Z)
+    return t
+
+
+def time_grad(torch, ts, X, steps):
+    ts.fitness_grad(X, precision="fp32")
+    with Timer(torch) as t:
+        for _ in range(steps):
+            ts.fitness_grad(X, precision="fp32")
+    return t
+
+
+def uneven_batching(args, api, torch, W, dev):
+    wl = W.config3()
+    s = wl.structs
+    P = wl.population.shape[0]
+    log(f"workload: {wl.name}; atoms {s.n_atoms}, population {P}")
+    ts, _, t_create = make_set(api, torch, wl)
+    st = ts.stats()
+    flop_cand, _ = set_flops(ts, s.n_atoms)
+    X = torch.as_tensor(wl.population, dtype=torch.float64, device=dev).contiguous()
+    Z = torch.empty(P, 4, dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    if not args.no_tune:
+        ts.autotune(P, "fp32", args.tune_cache)
+    t_tune = time.perf_counter() - t0
+    t, prof = time_generations(torch, ts, X, Z, args.uneven_steps, 2)
+    units = P * s.n_atoms
+    kernel_ms = prof[0] / args.uneven_steps
+    out = {"workload": wl.name, "value": units * args.uneven_steps / t.seconds,
+           "unit": "atom·candidate evals/s", "ms_per_step": t.seconds / args.uneven_steps * 1e3,
+           "steps": args.uneven_steps, "atoms": s.n_atoms, "structures": s.n_struct,
+           "bonds": st["n_bonds"], "triplets": st["n_triplets"], "population": P,
+           "batched_kernels_ms_per_step": kernel_ms,
+           "batched_launches_per_step": prof[1] / args.uneven_steps,
+           "algorithmic_tflops": flop_cand * P / (kernel_ms * 1e-3) / 1e12,
+           "setup_ms": {"set_create": t_create * 1e3, "autotune": t_tune * 1e3},
+           "seeds": wl.seeds}
+    log(f"uneven batched: {out['ms_per_step']:.3f} ms/generation, {out['value']:.4e} atom*cand/s, "
+        f"kernels {kernel_ms:.3f} ms ({out['algorithmic_tflops']:.2f} TFLOP/s)")
+    if args.plain_steps > 0:
+        tp = time_plain(torch, ts, X, Z, args.plain_steps)
+        out["plain"] = {"value": units * args.plain_steps / tp.seconds,
+                        "ms_per_step": tp.seconds / args.plain_steps * 1e3,
+                        "launches_per_step": P * s.n_struct}
+        log(f"uneven plain: {out['plain']['ms_per_step']:.1f} ms/generation")
+    ts.close()
+    return out
+
+
+def uneven_gradient(args, api, torch, W, dev):
+    wl = W.config4()
+    s = wl.structs
+    P = wl.population.shape[0]
+    ts, _, _ = make_set(api, torch, wl)
+    X = torch.as_tensor(wl.population, dtype=torch.float64, device=dev).contiguous()
+    if not args.no_tune:
+        ts.autotune(P, "fp32", args.tune_cache)
+    t = time_grad(torch, ts, X, args.uneven_grad_steps)
+    out = {"workload": wl.name, "value": P * s.n_atoms * args.uneven_grad_steps / t.seconds,
+           "unit": "atom·candidate fitness-grad evals/s",
+           "ms_per_step": t.seconds / args.uneven_grad_steps * 1e3,
+           "steps": args.uneven_grad_steps, "population": P, "seeds": wl.seeds}
+    log(f"uneven gradient: {out['ms_per_step']:.3f} ms/call, {out['value']:.4e} atom*cand/s")
+    ts.close()
+    return out
+
+
+def force_call(args, api, torch, W, dev):
+    wl = W.config5()
+    s = wl.structs
+    t0 = time.perf_counter()
+    ts = api.from_structures(s, R1=wl.R1, R2=wl.R2)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    vel = torch.as_tensor(wl.velocities, dtype=torch.float64, device=dev)
+    out = {"workload": wl.name, "atoms": s.n_atoms, "steps": args.md_steps,
+           "outputs": "energy, forces, virial, per-atom virial, heat current",
+           "set_create_ms": t_create * 1e3}
+    for prec in ("fp32", "fp64"):
+        ts.tersoff_eval(wl.population, precision=prec, atom_virial=True, velocities=vel)
+        with Timer(torch) as t:
+            for _ in range(args.md_steps):
+                ts.tersoff_eval(wl.population, precision=prec, atom_virial=True, velocities=vel)
+        out[prec] = {"ms_per_call": t.seconds / args.md_steps * 1e3,
+                     "atoms_per_s": s.n_atoms * args.md_steps / t.seconds}
+        log(f"64k force call {prec}: {out[prec]['ms_per_call']:.3f} ms/call")
+    ts.close()
+    return out
 
 
 def main():
@@ -75,31 +240,15 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
 
-    wl = W.config2() if args.workload == "config2" else W.config3()
+    wl = W.config2()
     s = wl.structs
     P = wl.population.shape[0]
     log(f"workload: {wl.name}; atoms {s.n_atoms}, structures {s.n_struct}, population {P}")
-
-    t0 = time.perf_counter()
-    ts = api.from_structures(s, R1=wl.R1, R2=wl.R2)
-    torch.cuda.synchronize()
-    t_create = time.perf_counter() - t0
+    ts, (e_ref, w_ref, f_ref), t_create = make_set(api, torch, wl)
     st = ts.stats()
     log("set:", st, f"created in {t_create * 1e3:.1f} ms")
-
-    # Reference data: the hidden parameter set evaluated by the float64 path.
-    ref = ts.tersoff_eval(wl.hidden_x[None], precision="fp64", forces=True, virial=True)
-    n = torch.as_tensor(s.sizes().astype(np.float64), device=dev)
-    e_ref = ref["E"][0] / n
-    w_ref = ref["W"][0] / n[:, None]
-    f_ref = ref["F"][0]
-    ts.attach_reference(e_ref, w_ref, f_ref)
-
-    i, _, _ = ts.neighbors()
-    M = np.bincount(i, minlength=s.n_atoms)
-    flop_cand = float(flops_per_atom(M).sum())          # one candidate, all atoms
+    flop_cand, trans_cand = set_flops(ts, s.n_atoms)
     flop_launch = flop_cand * P
-    trans_cand = float(6 * M.sum())
 
     X = torch.as_tensor(wl.population, dtype=torch.float64, device=dev).contiguous()
     Z = torch.empty(P, 4, dtype=torch.float64, device=dev)
@@ -108,79 +257,39 @@ def main():
         ts.autotune(P, "fp32", args.tune_cache)
     t_tune = time.perf_counter() - t0
 
-    call = ts.fitness_call(X, Z, precision="fp32", schedule="batched")
-    for _ in range(args.warmup):
-        call()
-    torch.cuda.synchronize()
-
-    # ---- timed region: K generations, graph replay --------------------------
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    e0.record()
-    for _ in range(args.steps):
-        call()
-    e1.record()
-    t_enq = time.perf_counter() - w0          # host time to enqueue the generations
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    t_steps = e0.elapsed_time(e1) / 1e3
-    ms_step = t_steps / args.steps * 1e3
+    # ---- timed region: K generations; then the kernel alone -----------------
+    t, prof = time_generations(torch, ts, X, Z, args.steps, args.warmup)
+    ms_step = t.seconds / args.steps * 1e3
     units = P * s.n_atoms
-    value = units * args.steps / t_steps
+    value = units * args.steps / t.seconds
     log(f"batched: {ms_step:.4f} ms/generation, {value:.4e} atom*cand/s "
-        f"(wall {wall * 1e3:.3f} ms, host enqueue {t_enq * 1e3:.3f} ms for {args.steps} generations)")
-
-    # ---- kernel duration with HIP events around each batched-kernel launch --
-    ts.profile(True)
-    ts.profile_read()
-    for _ in range(args.steps):
-        call()
-    torch.cuda.synchronize()
-    prof = ts.profile_read()["batched"]
-    ts.profile(False)
+        f"(wall {t.wall * 1e3:.3f} ms, host enqueue {t.enqueue * 1e3:.3f} ms for {args.steps} generations)")
     kernel_ms = prof[0] / max(prof[1], 1)
     achieved = flop_launch / (kernel_ms * 1e-3) / 1e12
     log(f"batched kernel: {kernel_ms:.4f} ms/launch over {prof[1]} launches, "
         f"{achieved:.2f} TFLOP/s algorithmic")
     Zb = Z.clone()
 
-    # ---- plain path: one launch per (candidate, structure) -------------------
     plain = None
     if args.plain_steps > 0:
-        ts.fitness(X, precision="fp32", schedule="plain", out=Z)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.plain_steps):
-            ts.fitness(X, precision="fp32", schedule="plain", out=Z)
-        e1.record()
-        torch.cuda.synchronize()
-        tp = e0.elapsed_time(e1) / 1e3
-        plain = {"value": units * args.plain_steps / tp, "ms_per_step": tp / args.plain_steps * 1e3,
+        tp = time_plain(torch, ts, X, Z, args.plain_steps)
+        plain = {"value": units * args.plain_steps / tp.seconds,
+                 "ms_per_step": tp.seconds / args.plain_steps * 1e3,
                  "launches_per_step": P * s.n_struct, "steps": args.plain_steps,
                  "max_abs_dZ_vs_batched": float((Z - Zb).abs().max())}
         log(f"plain: {plain['ms_per_step']:.2f} ms/generation, {plain['value']:.4e} atom*cand/s")
 
-    # ---- fitness gradient ----------------------------------------------------
     grad = None
     if args.grad_steps > 0:
-        ts.fitness_grad(X, precision="fp32")
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.grad_steps):
-            ts.fitness_grad(X, precision="fp32")
-        e1.record()
-        torch.cuda.synchronize()
-        tg = e0.elapsed_time(e1) / 1e3
-        grad = {"value": units * args.grad_steps / tg, "ms_per_step": tg / args.grad_steps * 1e3,
-                "steps": args.grad_steps}
+        tg = time_grad(torch, ts, X, args.grad_steps)
+        grad = {"value": units * args.grad_steps / tg.seconds,
+                "unit": "atom·candidate fitness-grad evals/s",
+                "ms_per_step": tg.seconds / args.grad_steps * 1e3, "steps": args.grad_steps}
         log(f"fitness_grad: {grad['ms_per_step']:.3f} ms/generation, {grad['value']:.4e} atom*cand/s")
 
     # ---- CPU oracle on a bounded sample --------------------------------------
     cpu = None
     if not args.no_cpu_baseline:
-        import torch as _t
         from oracle import tersoff as T
         refs = {"e": e_ref.cpu().numpy(), "w": w_ref.cpu().numpy(), "f": f_ref.cpu().numpy()}
         top = T.topology(s, wl.R2)
@@ -193,12 +302,21 @@ def main():
             T.fitness(s, wl.population[k:k + 1], refs, topology=top)
             done += 1
         tc = time.perf_counter() - c0
-        cpu = {"value": done * s.n_atoms / tc, "unit": "atom*candidate evals/s",
-               "cores": int(_t.get_num_threads()), "kind": "oracle",
+        cpu = {"value": done * s.n_atoms / tc, "unit": "atom·candidate evals/s",
+               "cores": int(torch.get_num_threads()), "kind": "oracle",
                "sample": f"{done} candidate evaluations (population of {P}, in order, wrapping) x "
                          f"all {s.n_struct} structures = {done * s.n_atoms} atom*candidate evals "
                          f"in {tc:.1f} s, float64 autograd"}
         log(f"cpu oracle: {cpu['value']:.4e} atom*cand/s on {cpu['cores']} threads")
+    ts.close()
+
+    workloads = {}
+    if args.uneven_steps > 0:
+        workloads["uneven_batching"] = uneven_batching(args, api, torch, W, dev)
+    if args.uneven_grad_steps > 0:
+        workloads["uneven_gradient"] = uneven_gradient(args, api, torch, W, dev)
+    if args.md_steps > 0:
+        workloads["force_call_64k"] = force_call(args, api, torch, W, dev)
 
     line = {
         "metric": "atom·candidate Tersoff force evals/s and fitness-grad evals/s, batched vs plain",
@@ -215,14 +333,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "population": P, "structures": s.n_struct,
                    "atoms": s.n_atoms, "bonds": st["n_bonds"], "triplets": st["n_triplets"],
-                   "precision": "f32 arithmetic, f64 accumulation", "schedule": "batched, HIP graph",
+                   "precision": "f32 arithmetic, f64 accumulation", "schedule": "batched",
                    "parallelism": "single GPU", "seeds": wl.seeds},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": None},
-        "kernel": {"name": "k_batched<float, fit>", "avg_ms": kernel_ms, "launches": prof[1],
+        "kernel": {"name": "k_batched<float, fit, M<=4>", "avg_ms": kernel_ms, "launches": prof[1],
                    "flop_per_launch": flop_launch, "transcendentals_per_launch": trans_cand * P},
+        "host_enqueue_ms_per_step": t.enqueue / args.steps * 1e3,
         "plain": plain,
         "fitness_grad": grad,
+        "workloads": workloads,
         "cpu_baseline": cpu,
         "setup_ms": {"set_create": t_create * 1e3, "autotune": t_tune * 1e3},
     }

@@ -182,9 +182,14 @@ int fitness_grad(mt_set* set, const double* x, int P, const double* w, int preci
 /*
  * Choose launch shapes (block size, candidate tile, schedule) for this set
  * and population size by timing the candidates on the GPU; the choice is kept
- * in the set and used by later calls with the same P and precision.  When
- * cache_path is not NULL the choice is also appended to that text file, and a
- * matching entry already there is used without timing.
+ * in the set and used by later calls with the same P and precision.  With
+ * reference data attached it also chooses between replaying a captured graph
+ * per fitness_eval call and launching the kernels directly, by the host-clock
+ * rate of a burst of back-to-back calls.  When cache_path is not NULL every
+ * timing is appended to that text file as a comment line ("# ...") and the
+ * choice as a line "<set key> | block=B tile=T persistent=0|1 graph=0|1 ms=..";
+ * a matching entry already there is used without timing.  Calls that overlap
+ * on one set race (the set's workspace is shared).
  */
 int mt_autotune(mt_set* set, int P, int precision, const char* cache_path);
 

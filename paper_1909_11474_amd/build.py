@@ -4,7 +4,8 @@
 
 Every .hip source under csrc/ is compiled with hipcc for gfx950 and linked
 into paper_1909_11474_amd/libmt_tersoff.so.  Packed-FP32 instructions are
-disabled for all device code.
+disabled for all device code, and floating-point contraction is limited to
+single source expressions.
 """
 from __future__ import annotations
 
@@ -28,6 +29,11 @@ CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fno-signed-zeros",
+    # multiply-adds fuse only where one source expression has them: the same
+    # site routine inlined into different kernels (batched, plain, two-pass)
+    # then rounds identically, which keeps float64 results bit-identical
+    # across schedules
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]

@@ -14,7 +14,7 @@
 //                     relative to st_boff[s]), xbase[a] (exchange slot, below)
 //   per bond slot   : slot-major arrays [m][N] (m < kcap) of float and double
 //                     geometry: unit vector, length (float: hi+lo split), 1/r,
-//                     f_C(r), f_C'(r); int: exchange slot and CSR index of the
+//                     f_C(r), f_C'(r)/2; int: exchange slot and CSR index of the
 //                     reverse bond, neighbour atom (structure-local sorted index).
 //
 // Exchange slots (LDS of the batched kernels).  A replica of structure s is cut
@@ -49,12 +49,13 @@ enum ParamIndex {
     P_R0LO = 2,     // r0 - r0_hi (float only)
     P_D0 = 3,
     P_2D0 = 4,
-    P_ALPHA = 5,
     P_BETA = 6,
     P_N = 7,
     P_NINV2N = 8,   // -1 / (2 n)
     P_H = 9,
-    P_VALID = 10    // 1 if the candidate is inside the potential's domain
+    P_VALID = 10,   // 1 if the candidate is inside the potential's domain
+    P_HALPHA = 11,  // alpha / 2
+    P_HBETA = 12    // beta / 2
 };
 
 struct Item {       // one (structure, candidate range) work item of the batched kernel
@@ -68,9 +69,9 @@ template <typename S>
 struct GeomArrays {
     const S* ux; const S* uy; const S* uz;
     const S* rhi; const S* rlo; const S* rinv;
-    const S* fc; const S* fcp;
+    const S* fc; const S* hfcp;     // f_C and f_C'/2
     // float only: the same geometry packed per bond slot as two 4-vectors,
-    // (ux, uy, uz, r_hi) and (r_lo, 1/r, f_C, f_C'), [kcap][N] each
+    // (ux, uy, uz, r_hi) and (r_lo, 1/r, f_C, f_C'/2), [kcap][N] each
     const float4* pk0; const float4* pk1;
 };
 

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <numeric>
 #include <queue>
+#include <string>
 #include <vector>
 
 #include "mt_kernels.h"
@@ -282,6 +283,28 @@ static bool upload_class(ClassPlan& cp, const std::vector<Item>& ordered, const 
     return hipMemcpy(cp.bin_off.p, bin_off.data(), sizeof(int) * bin_off.size(), hipMemcpyHostToDevice) == hipSuccess;
 }
 
+// Candidate tile of structure s at R replicas per block (whole steps of the replicas).
+static int tile_for(const LaunchCfg& cfg, int P, int R, bool plain) {
+    int tile = plain ? 1 : std::max(cfg.tile, 1);
+    if (!plain) tile = ((tile + R - 1) / R) * R;
+    return std::min(tile, ((P + R - 1) / R) * R);
+}
+
+// Block size for structure s: the requested one, or the largest smaller
+// multiple of the padded size (at least 64 threads) whose LDS fits the
+// device; 0 when a single replica does not fit.
+static int block_for(const mt_set* set, int s, const LaunchCfg& cfg, int P, int fam, bool plain) {
+    const int npad = set->h_npad[s];
+    const int step = std::max(64, npad);
+    int block = plain ? step : (cfg.block / step) * step;
+    for (; block >= step; block -= step) {
+        const int R = block / npad;
+        if (item_lds(set, s, block, fam, std::min(tile_for(cfg, P, R, plain), P)) <= set->lds_max)
+            return block;
+    }
+    return 0;
+}
+
 // cfg.block == 0 requests the plain plan: one item per (structure, candidate).
 ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int fam) {
     auto key = std::make_tuple(P, cfg.block, cfg.tile, cfg.persistent, fam);
@@ -297,21 +320,27 @@ ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int fam) {
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
             ncu = prop.multiProcessorCount;
     }
-    for (int mc : family_classes(fam)) {
+    struct Group {
         std::vector<Item> items;
         size_t lds = 16;
         int ptile = 1;
+    };
+    for (int mc : family_classes(fam)) {
+        std::map<int, Group> groups;          // launch block size -> work items
         for (int s = 0; s < set->S; ++s) {
             if (set->h_large[s] || class_of(fam, set->h_kmax[s]) != mc) continue;
             const int npad = set->h_npad[s];
-            const int block = plain ? std::max(64, npad) : cfg.block;
+            if (!plain && cfg.block < npad) return nullptr;
+            const int block = block_for(set, s, cfg, P, fam, plain);
+            if (block == 0) {
+                plan->twopass.push_back(s);
+                continue;
+            }
             const int R = block / npad;
-            if (R < 1) return nullptr;
-            int tile = plain ? 1 : std::max(cfg.tile, 1);
-            if (!plain) tile = ((tile + R - 1) / R) * R;      // whole steps of the replicas
-            tile = std::min(tile, ((P + R - 1) / R) * R);
-            ptile = std::max(ptile, std::min(tile, P));
-            lds = std::max(lds, item_lds(set, s, block, fam, std::min(tile, P)));
+            const int tile = tile_for(cfg, P, R, plain);
+            Group& g = groups[block];
+            g.ptile = std::max(g.ptile, std::min(tile, P));
+            g.lds = std::max(g.lds, item_lds(set, s, block, fam, std::min(tile, P)));
             const int ns = set->h_off[s + 1] - set->h_off[s];
             for (int c0 = 0; c0 < P; c0 += tile) {
                 Item it;
@@ -321,53 +350,56 @@ ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int fam) {
                 const long long steps = (it.nc + R - 1) / R;
                 const long long per = set->h_trip[s] + 8ll * ns + 64;
                 it.cost = (int)std::min<long long>(steps * per / std::max(1, R) + 1, 1ll << 30);
-                items.push_back(it);
+                g.items.push_back(it);
             }
         }
-        if (items.empty()) continue;
-        auto cp = std::make_unique<ClassPlan>();
-        cp->mc = mc;
-        cp->lds = lds;
-        cp->ptile = ptile;
-        std::vector<int> bin_off;
-        std::vector<Item> ordered;
-        if (plain) {
-            ordered = items;
-            bin_off = {0, 1};
-        } else {
-            // candidate-tile-major among equal costs, so that the candidates of
-            // early tiles complete (and can be finalized) while later tiles run
-            std::stable_sort(items.begin(), items.end(),
-                             [](const Item& a, const Item& b) { return a.c0 < b.c0; });
-            std::stable_sort(items.begin(), items.end(),
-                             [](const Item& a, const Item& b) { return a.cost > b.cost; });
-            if (!cfg.persistent) {
+        for (auto it = groups.rbegin(); it != groups.rend(); ++it) {
+            std::vector<Item>& items = it->second.items;
+            auto cp = std::make_unique<ClassPlan>();
+            cp->mc = mc;
+            cp->block = it->first;
+            cp->lds = it->second.lds;
+            cp->ptile = it->second.ptile;
+            std::vector<int> bin_off;
+            std::vector<Item> ordered;
+            if (plain) {
                 ordered = items;
-                bin_off.resize(items.size() + 1);
-                std::iota(bin_off.begin(), bin_off.end(), 0);
+                bin_off = {0, 1};
             } else {
-                const int per_cu = std::max(1, 1024 / cfg.block);
-                const int nbins = (int)std::min<size_t>(items.size(), (size_t)ncu * per_cu);
-                std::vector<std::vector<Item>> bins(std::max(nbins, 1));
-                using E = std::pair<long long, int>;
-                std::priority_queue<E, std::vector<E>, std::greater<E>> heap;
-                for (int b = 0; b < (int)bins.size(); ++b) heap.push({0, b});
-                for (const Item& it : items) {      // longest first onto the least-loaded bin
-                    E e = heap.top();
-                    heap.pop();
-                    bins[e.second].push_back(it);
-                    heap.push({e.first + it.cost, e.second});
-                }
-                bin_off.push_back(0);
-                for (auto& b : bins) {
-                    for (auto& it : b) ordered.push_back(it);
-                    bin_off.push_back((int)ordered.size());
+                // candidate-tile-major among equal costs, so that the candidates of
+                // early tiles complete while later tiles run
+                std::stable_sort(items.begin(), items.end(),
+                                 [](const Item& a, const Item& b) { return a.c0 < b.c0; });
+                std::stable_sort(items.begin(), items.end(),
+                                 [](const Item& a, const Item& b) { return a.cost > b.cost; });
+                if (!cfg.persistent) {
+                    ordered = items;
+                    bin_off.resize(items.size() + 1);
+                    std::iota(bin_off.begin(), bin_off.end(), 0);
+                } else {
+                    const int per_cu = std::max(1, 1024 / cp->block);
+                    const int nbins = (int)std::min<size_t>(items.size(), (size_t)ncu * per_cu);
+                    std::vector<std::vector<Item>> bins(std::max(nbins, 1));
+                    using E = std::pair<long long, int>;
+                    std::priority_queue<E, std::vector<E>, std::greater<E>> heap;
+                    for (int b = 0; b < (int)bins.size(); ++b) heap.push({0, b});
+                    for (const Item& w : items) {       // longest first onto the least-loaded bin
+                        E e = heap.top();
+                        heap.pop();
+                        bins[e.second].push_back(w);
+                        heap.push({e.first + w.cost, e.second});
+                    }
+                    bin_off.push_back(0);
+                    for (auto& b : bins) {
+                        for (auto& w : b) ordered.push_back(w);
+                        bin_off.push_back((int)ordered.size());
+                    }
                 }
             }
+            if (!upload_class(*cp, ordered, bin_off)) return nullptr;
+            if (plain) cp->n_bins = 1;
+            plan->cls.push_back(std::move(cp));
         }
-        if (!upload_class(*cp, ordered, bin_off)) return nullptr;
-        if (plain) cp->n_bins = 1;
-        plan->cls.push_back(std::move(cp));
     }
     ItemPlan* raw = plan.get();
     set->plans[key] = std::move(plan);
@@ -386,14 +418,14 @@ static int run_plan(mt_set* set, ItemPlan* plan, const LaunchCfg& cfg, int fam, 
             Af.items = Ad.items = cp.items.as<Item>();
             Af.bin_off = Ad.bin_off = cp.bin_off.as<int>();
             ProfScope prof(set, prof_kind);
-            HIPCHECK(launch_family(fam, cp.mc, dim3(cp.n_bins), dim3(cfg.block), cp.lds, st, Af, Ad,
+            HIPCHECK(launch_family(fam, cp.mc, dim3(cp.n_bins), dim3(cp.block), cp.lds, st, Af, Ad,
                                    prof.e0, prof.e1));
         } else {
             const bool f64 = fam == FAM_FIT64 || fam == FAM_EVAL64;
             const int mode = (fam == FAM_FIT32 || fam == FAM_FIT64) ? MODE_FIT : MODE_EVAL;
             for (int k = 0; k < cp.n_items; ++k) {
                 const int s = cp.h_items[k].s;
-                const dim3 block(std::max(64, set->h_npad[s]));
+                const dim3 block(cp.block);
                 const size_t lds = item_lds(set, s, block.x, fam, 1);
                 Af.items = Ad.items = cp.items.as<Item>() + k;
                 HIPCHECK(f64 ? launch_plain64(mode, cp.mc, block, lds, st, Ad)
@@ -403,6 +435,10 @@ static int run_plan(mt_set* set, ItemPlan* plan, const LaunchCfg& cfg, int fam, 
     }
     return MT_OK;
 }
+
+static int launch_twopass(mt_set* set, const std::vector<int>& structs, int P, int precision,
+                          int mode, const double* vel, double* force, double* atom_virial,
+                          hipStream_t st);
 
 int launch_batched(mt_set* set, const LaunchCfg& cfg, int P, int precision, int mode,
                    const double* vel, double* force, double* atom_virial, hipStream_t st) {
@@ -418,7 +454,10 @@ int launch_batched(mt_set* set, const LaunchCfg& cfg, int P, int precision, int 
     Af.vel = Ad.vel = vel;
     Af.force = Ad.force = force;
     Af.atom_virial = Ad.atom_virial = atom_virial;
-    return run_plan(set, plan, cfg, fam, Af, Ad, 0, st);
+    TRY_RC(run_plan(set, plan, cfg, fam, Af, Ad, 0, st));
+    if (plan->twopass.empty()) return MT_OK;
+    TRY_RC(reserve_twopass(set, plan, P, precision));     // no-op once reserved
+    return launch_twopass(set, plan->twopass, P, precision, mode, vel, force, atom_virial, st);
 }
 
 int launch_plain(mt_set* set, int P, int precision, int mode, const double* vel, double* force,
@@ -427,22 +466,47 @@ int launch_plain(mt_set* set, int P, int precision, int mode, const double* vel,
     return launch_batched(set, plain, P, precision, mode, vel, force, atom_virial, st);
 }
 
+// Candidates per launch of the two-pass path for structure s: bounded so that
+// the bond-gradient staging buffer stays within 256 MB.
+static int twopass_chunk(const mt_set* set, int s, int P, size_t elem) {
+    const size_t per = 3 * (size_t)(set->h_boff[s + 1] - set->h_boff[s]) * elem;
+    const size_t chunk = std::min<size_t>((size_t)P, (256ull << 20) / std::max<size_t>(per, 1));
+    return (int)std::min<size_t>(std::max<size_t>(chunk, 1), 65535);
+}
+
+int reserve_twopass(mt_set* set, const ItemPlan* plan, int P, int precision) {
+    const size_t elem = precision == MT_FP64 ? sizeof(double) : sizeof(float);
+    size_t need = 0;
+    auto add = [&](int s) {
+        const size_t per = 3 * (size_t)(set->h_boff[s + 1] - set->h_boff[s]) * elem;
+        need = std::max(need, per * twopass_chunk(set, s, P, elem));
+    };
+    for (int s = 0; s < set->S; ++s)
+        if (set->h_large[s]) add(s);
+    if (plan)
+        for (int s : plan->twopass) add(s);
+    if (need) HIPCHECK(set->gbuf.reserve(need));
+    return MT_OK;
+}
+
+// Two-pass evaluation (bond gradients staged in global memory, then gathered)
+// of the listed structures, for structures too large for one block's LDS.
 template <typename S>
-static int launch_large_t(mt_set* set, int P, int mode, int nv, const double* vel, double* force,
-                          double* atom_virial, hipStream_t st) {
+static int launch_twopass_t(mt_set* set, const std::vector<int>& structs, int P, int mode, int nv,
+                            const double* vel, double* force, double* atom_virial, hipStream_t st) {
     BArgs<S> A = make_args<S>(set, set->partial.as<double>(), nv);
     A.vel = vel;
     A.force = force;
     A.atom_virial = atom_virial;
-    for (int s = 0; s < set->S; ++s) {
-        if (!set->h_large[s]) continue;
+    for (int s : structs) {
         const int mc = set->h_kmax[s] <= 4 ? 4 : 16;
         const int ns = set->h_off[s + 1] - set->h_off[s];
-        const size_t nbs = (size_t)(set->h_boff[s + 1] - set->h_boff[s]);
-        const size_t per = 3 * nbs * sizeof(S);
-        int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)P, (256ull << 20) / std::max<size_t>(per, 1)));
-        chunk = std::min(chunk, 65535);
-        HIPCHECK(set->gbuf.reserve(per * chunk));
+        const size_t per = 3 * (size_t)(set->h_boff[s + 1] - set->h_boff[s]) * sizeof(S);
+        const int chunk = twopass_chunk(set, s, P, sizeof(S));
+        if (set->gbuf.bytes < per * chunk) {
+            set_error("two-pass staging buffer not reserved");
+            return MT_ESTATE;
+        }
         for (int c0 = 0; c0 < P; c0 += chunk) {
             const int nc = std::min(chunk, P - c0);
             LArgs L{s, c0, set->gbuf.p};
@@ -458,12 +522,24 @@ static int launch_large_t(mt_set* set, int P, int mode, int nv, const double* ve
     return MT_OK;
 }
 
+static int launch_twopass(mt_set* set, const std::vector<int>& structs, int P, int precision,
+                          int mode, const double* vel, double* force, double* atom_virial,
+                          hipStream_t st) {
+    if (structs.empty()) return MT_OK;
+    const int nv = mode == MODE_FIT ? kNVFit : kNVEval;
+    return precision == MT_FP64
+               ? launch_twopass_t<double>(set, structs, P, mode, nv, vel, force, atom_virial, st)
+               : launch_twopass_t<float>(set, structs, P, mode, nv, vel, force, atom_virial, st);
+}
+
 int launch_large(mt_set* set, int P, int precision, int mode, const double* vel, double* force,
                  double* atom_virial, hipStream_t st) {
     if (set->n_large == 0) return MT_OK;
-    const int nv = mode == MODE_FIT ? kNVFit : kNVEval;
-    return precision == MT_FP64 ? launch_large_t<double>(set, P, mode, nv, vel, force, atom_virial, st)
-                                : launch_large_t<float>(set, P, mode, nv, vel, force, atom_virial, st);
+    std::vector<int> structs;
+    for (int s = 0; s < set->S; ++s)
+        if (set->h_large[s]) structs.push_back(s);
+    TRY_RC(reserve_twopass(set, nullptr, P, precision));
+    return launch_twopass(set, structs, P, precision, mode, vel, force, atom_virial, st);
 }
 
 int launch_finalize_fit(mt_set* set, int P, const double* w, double* Z, hipStream_t st) {
@@ -505,6 +581,13 @@ static int adjoint_common(mt_set* set, const LaunchCfg& cfg, int P, int precisio
     ItemPlan* plan = get_plan(set, P, cfg, fam);
     if (!plan) {
         set_error("could not build the adjoint work list");
+        return MT_EINVAL;
+    }
+    if (!plan->twopass.empty()) {
+        const int s = plan->twopass.front();
+        set_error("fitness_grad: structure " + std::to_string(s) + " (" +
+                  std::to_string(set->h_off[s + 1] - set->h_off[s]) +
+                  " atoms) does not fit one block's LDS in this precision");
         return MT_EINVAL;
     }
     BArgs<float> Af = make_args<float>(set, set->partial2.as<double>(), kNVGrad);

@@ -41,10 +41,12 @@ struct LaunchCfg {            // launch shape of the batched kernel
     int block = 0;            // threads per block, multiple of 64, >= largest padded structure
     int tile = 0;             // candidates per work item (0: derived from the block)
     int persistent = 0;       // 1: static LPT bins over a fixed grid; 0: one block per item
+    int graph = 1;            // fitness_eval: 1 replays a captured graph, 0 launches directly
 };
 
-struct ClassPlan {            // work list of one coordination class
+struct ClassPlan {            // work list of one launch: a coordination class at one block size
     int mc = 0;               // class: largest coordination the kernel instance serves
+    int block = 0;            // threads per block of this launch
     DevBuf items;             // Item[n_items]
     DevBuf bin_off;           // int[n_bins + 1]
     std::vector<Item> h_items;
@@ -56,6 +58,9 @@ struct ClassPlan {            // work list of one coordination class
 
 struct ItemPlan {             // uploaded work lists for one (P, launch shape, kernel family)
     std::vector<std::unique_ptr<ClassPlan>> cls;
+    // structures of at most MT_MAX_BATCHED_ATOMS atoms whose single replica does
+    // not fit the LDS of a block in this family: evaluated by the two-pass path
+    std::vector<int> twopass;
 };
 
 // Kernel families: precision x (fitness, energy/force/virial, adjoint).
@@ -85,6 +90,7 @@ struct mt_set {
     int S = 0, N = 0, kcap = 0, kmax = 0, nb = 0, nslots = 0;
     long long ntrip = 0;
     int max_atoms = 0, n_batched = 0, n_large = 0;
+    size_t lds_max = 65536;   // dynamic LDS bytes a block may use on the set's device
     double R1 = 0, R2 = 0;
     int device = 0;
 
@@ -146,6 +152,9 @@ int launch_plain(mt_set* set, int P, int precision, int mode, const double* vel,
                  double* atom_virial, hipStream_t stream);
 int launch_large(mt_set* set, int P, int precision, int mode, const double* vel, double* force,
                  double* atom_virial, hipStream_t stream);
+// Reserve the two-pass staging buffer for the set's large structures and the
+// plan's two-pass structures (before graph capture: capture may not allocate).
+int reserve_twopass(mt_set* set, const ItemPlan* plan, int P, int precision);
 int launch_finalize_fit(mt_set* set, int P, const double* w, double* Z, hipStream_t stream);
 int launch_finalize_eval(mt_set* set, int P, double* energy, double* virial, double* heat,
                          hipStream_t stream);

@@ -59,12 +59,13 @@ __device__ __forceinline__ void decode_record(const double* __restrict__ x, S* _
     o[P_R0LO] = (S)(r0 - (double)r0hi);
     o[P_D0] = (S)D0;
     o[P_2D0] = (S)(2.0 * D0);
-    o[P_ALPHA] = (S)al;
     o[P_BETA] = (S)be;
     o[P_N] = (S)n;
     o[P_NINV2N] = (S)(-1.0 / (2.0 * n));
     o[P_H] = (S)h;
     o[P_VALID] = ok ? S(1) : S(0);
+    o[P_HALPHA] = (S)(0.5 * al);
+    o[P_HBETA] = (S)(0.5 * be);
 }
 
 template <typename S>
@@ -473,14 +474,14 @@ struct LArgs {
 };
 
 template <typename S, int M>
-__device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L, int atom, bool active) {
+__device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L, int la, int atom,
+                                               bool active) {
     const SetDev& d = A.set;
     const int N = d.N;
     Geo<S, M> g;
     g.load(geom_of<S>(d), N, atom, active);
     constexpr int MM = M > 0 ? M : 1;
     const int c = L.c0 + blockIdx.y;
-    const int a0 = d.st_off[L.s];
     const int nbs = d.st_boff[L.s + 1] - d.st_boff[L.s];
     const int Mi = active ? d.nnb[atom] : 0;
     const int lb = active ? d.lbo[atom] : 0;
@@ -518,7 +519,8 @@ __device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L
     int vidx;
     const double sum = group_reduce8(v, 64, &vidx);
     const int lane = threadIdx.x & 63;
-    const int slot = d.st_slot[L.s] + ((atom - a0) >> 6);
+    // one slot per wavefront of the structure (inactive tail lanes included)
+    const int slot = d.st_slot[L.s] + (la >> 6);
     if ((lane & 7) == 0 && vidx < 7)
         A.partial[((size_t)c * d.nslots + slot) * A.nv + vidx] = sum;
 }
@@ -534,7 +536,7 @@ __global__ __launch_bounds__(256) void k_large_site(BArgs<S> A, LArgs L) {
     const int Mw = wave_max_int(Mi);
     if (Mw < 0) return;
     dispatch_m<ClassLo<MC>::value, MC>(Mw, [&](auto mv) {
-        run_large_site<S, decltype(mv)::value>(A, L, atom, active);
+        run_large_site<S, decltype(mv)::value>(A, L, la, atom, active);
     });
 }
 
@@ -545,6 +547,8 @@ __global__ __launch_bounds__(256) void k_large_gather(BArgs<S> A, LArgs L) {
     const int a0 = d.st_off[L.s], Ns = d.st_off[L.s + 1] - a0;
     const int nbs = d.st_boff[L.s + 1] - d.st_boff[L.s];
     const int la = blockIdx.x * blockDim.x + threadIdx.x;
+    // wavefronts past the structure own no partial-sum slot (ceil(Ns / 64) slots)
+    if ((la & ~63) >= Ns) return;
     const bool active = la < Ns;
     const int atom = a0 + (active ? la : 0);
     const int c = L.c0 + blockIdx.y;

@@ -348,18 +348,18 @@ __global__ void k_geometry(int N, int S, int kcap, double R1, double R2,
     const int o = m * N + a;
     float* f_ux = gf;         float* f_uy = gf + KN;    float* f_uz = gf + 2 * KN;
     float* f_rhi = gf + 3 * KN; float* f_rinv = gf + 4 * KN;
-    float* f_fc = gf + 5 * KN;  float* f_fcp = gf + 6 * KN;
+    float* f_fc = gf + 5 * KN;  float* f_hfcp = gf + 6 * KN;
     double* d_ux = gd;        double* d_uy = gd + KN;   double* d_uz = gd + 2 * KN;
     double* d_r = gd + 3 * KN;  double* d_rinv = gd + 4 * KN;
-    double* d_fc = gd + 5 * KN; double* d_fcp = gd + 6 * KN;
+    double* d_fc = gd + 5 * KN; double* d_hfcp = gd + 6 * KN;
     const int s = struct_of(st_off, S, a);
     const int npad = st_npad[s];
     const int G = npad < 64 ? npad : 64;
     if (m >= M) {
         f_ux[o] = f_uy[o] = f_uz[o] = 0.f; f_rhi[o] = 3.0f; gf_rlo[o] = 0.f;
-        f_rinv[o] = 0.f; f_fc[o] = 0.f; f_fcp[o] = 0.f;
+        f_rinv[o] = 0.f; f_fc[o] = 0.f; f_hfcp[o] = 0.f;
         d_ux[o] = d_uy[o] = d_uz[o] = 0.0; d_r[o] = 3.0; d_rinv[o] = 0.0;
-        d_fc[o] = 0.0; d_fcp[o] = 0.0;
+        d_fc[o] = 0.0; d_hfcp[o] = 0.0;
         // a padded bond reads back its own (zero) slot and its own atom
         gpk[o] = make_float4(0.f, 0.f, 0.f, 3.0f);
         gpk[KN + o] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -379,24 +379,24 @@ __global__ void k_geometry(int N, int S, int kcap, double R1, double R2,
         dv[k] = pos[k * N + j] - pos[k * N + i] + n1 * me.h[k] + n2 * me.h[3 + k] + n3 * me.h[6 + k];
     const double r = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
     const double rinv = 1.0 / r;
-    double fc, fcp;
-    if (r <= R1) { fc = 1.0; fcp = 0.0; }
-    else if (r >= R2) { fc = 0.0; fcp = 0.0; }
+    double fc, hfcp;                 // f_C and f_C'/2 (the kernels only use half the slope)
+    if (r <= R1) { fc = 1.0; hfcp = 0.0; }
+    else if (r >= R2) { fc = 0.0; hfcp = 0.0; }
     else {
         const double w = M_PI / (R2 - R1);
         const double ph = w * (r - R1);
         fc = 0.5 * (1.0 + cos(ph));
-        fcp = -0.5 * w * sin(ph);
+        hfcp = -0.25 * w * sin(ph);
     }
     const double ux = dv[0] * rinv, uy = dv[1] * rinv, uz = dv[2] * rinv;
     d_ux[o] = ux; d_uy[o] = uy; d_uz[o] = uz; d_r[o] = r; d_rinv[o] = rinv;
-    d_fc[o] = fc; d_fcp[o] = fcp;
+    d_fc[o] = fc; d_hfcp[o] = hfcp;
     const float rhi = (float)r;
     f_ux[o] = (float)ux; f_uy[o] = (float)uy; f_uz[o] = (float)uz;
     f_rhi[o] = rhi; gf_rlo[o] = (float)(r - (double)rhi);
-    f_rinv[o] = (float)rinv; f_fc[o] = (float)fc; f_fcp[o] = (float)fcp;
+    f_rinv[o] = (float)rinv; f_fc[o] = (float)fc; f_hfcp[o] = (float)hfcp;
     gpk[o] = make_float4((float)ux, (float)uy, (float)uz, rhi);
-    gpk[KN + o] = make_float4((float)(r - (double)rhi), (float)rinv, (float)fc, (float)fcp);
+    gpk[KN + o] = make_float4((float)(r - (double)rhi), (float)rinv, (float)fc, (float)hfcp);
     // reverse entry: (j -> i, -shift) in j's sorted list
     const int want = pack_shift(-n1, -n2, -n3);
     const int Mj = cnt[j];
@@ -479,6 +479,10 @@ int grid_of(long long n, int block) { return (int)((n + block - 1) / block); }
 int build_set(mt_set* set, const int64_t* atom_offset, const double* pos, const double* cell,
               hipStream_t st) {
     const int S = set->S, N = set->N, kcap = set->kcap;
+    int dev = 0, lds_max = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    HIPCHECK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    set->lds_max = (size_t)lds_max;
     set->h_off.assign(S + 1, 0);
     for (int s = 0; s <= S; ++s) set->h_off[s] = (int)atom_offset[s];
 

@@ -13,11 +13,12 @@
 // coefficient of d zeta_ij, c~_j = 2 beta C_j, t_jk = cos_jk - h and
 // q_jk = (c~_j f_C,k + c~_k f_C,j) t_jk, the gradient decomposes into a radial
 // part along r^_j and a transverse sum:
-//   G_j = [ D_j + f_C'_j/2 sum_k c~_k t_jk^2 - (1/r_j) sum_k q_jk cos_jk ] r^_j
-//         + (1/r_j) sum_k q_jk r^_k,
-//   D_j = 1/2 [ f_C'_j (f_R - b f_A) + f_C,j alpha (b f_A - 2 f_R) ].
-// Every unordered bond pair (j, k) is visited once in each of the forward
-// (zeta) and backward (gradient) sweeps.
+//   G_j = [ D_j + f_C'_j/2 sum_k c~_k t_jk^2 - (1/r_j) r^_j . V_j ] r^_j + (1/r_j) V_j,
+//   V_j = sum_k q_jk r^_k,
+//   D_j = 1/2 [ f_C'_j (f_R - b f_A) + f_C,j alpha (b f_A - 2 f_R) ]
+// (the radial term uses sum_k q_jk cos_jk = r^_j . V_j).  Every unordered bond
+// pair (j, k) is visited once in each of the forward (zeta) and backward
+// (gradient) sweeps.
 //
 // V is the value type (float, double, or Dual<> for parameter derivatives);
 // S is the geometry type.  The code is written once for all of them.
@@ -33,7 +34,7 @@ struct Geo {
     static constexpr bool kCache = NP <= 15;       // keep cos(theta) in registers for M <= 6
     S ux[M > 0 ? M : 1], uy[M > 0 ? M : 1], uz[M > 0 ? M : 1];
     S rhi[M > 0 ? M : 1], rlo[M > 0 ? M : 1], rinv[M > 0 ? M : 1];
-    S fc[M > 0 ? M : 1], fcp[M > 0 ? M : 1];
+    S fc[M > 0 ? M : 1], hfcp[M > 0 ? M : 1];     // f_C and f_C'/2
     S cs[kCache && NP > 0 ? NP : 1];
 
     __device__ __forceinline__ S cosjk(int j, int k, int pidx) const {
@@ -54,7 +55,7 @@ struct Geo {
                     const float4 a = active ? G.pk0[o] : make_float4(0.f, 0.f, 0.f, 3.f);
                     const float4 b = active ? G.pk1[o] : make_float4(0.f, 0.f, 0.f, 0.f);
                     ux[m] = a.x; uy[m] = a.y; uz[m] = a.z; rhi[m] = a.w;
-                    rlo[m] = b.x; rinv[m] = b.y; fc[m] = b.z; fcp[m] = b.w;
+                    rlo[m] = b.x; rinv[m] = b.y; fc[m] = b.z; hfcp[m] = b.w;
                 }
                 cache_cos();
                 return;
@@ -70,7 +71,7 @@ struct Geo {
             rlo[m] = (active && G.rlo) ? G.rlo[o] : S(0);
             rinv[m] = active ? G.rinv[o] : S(0);
             fc[m] = active ? G.fc[o] : S(0);
-            fcp[m] = active ? G.fcp[o] : S(0);
+            hfcp[m] = active ? G.hfcp[o] : S(0);
         }
         cache_cos();
     }
@@ -88,14 +89,15 @@ struct Geo {
 
 template <typename V, typename S>
 struct Cand {
-    V aL, r0hi, r0lo, D0, twoD0, alpha, beta, n, ninv2n, h;
+    V aL, r0hi, r0lo, D0, twoD0, halpha, beta, hbeta, n, ninv2n, h;
     S valid;
 };
 
 template <typename S>
 __device__ __forceinline__ void load_cand(const S* __restrict__ p, Cand<S, S>& c) {
     c.aL = p[P_AL]; c.r0hi = p[P_R0HI]; c.r0lo = p[P_R0LO]; c.D0 = p[P_D0]; c.twoD0 = p[P_2D0];
-    c.alpha = p[P_ALPHA]; c.beta = p[P_BETA]; c.n = p[P_N]; c.ninv2n = p[P_NINV2N]; c.h = p[P_H];
+    c.halpha = p[P_HALPHA]; c.beta = p[P_BETA]; c.hbeta = p[P_HBETA];
+    c.n = p[P_N]; c.ninv2n = p[P_NINV2N]; c.h = p[P_H];
     c.valid = p[P_VALID];
 }
 
@@ -108,8 +110,9 @@ __device__ __forceinline__ void load_cand(const S* __restrict__ p, Cand<Dual<S>,
     c.r0lo = dconst<S>(p[P_R0LO]);
     c.D0 = dconst<S>(p[P_D0]);        c.D0.d[0] = S(1);
     c.twoD0 = dconst<S>(p[P_2D0]);    c.twoD0.d[0] = S(2);
-    c.alpha = dconst<S>(p[P_ALPHA]);  c.alpha.d[1] = S(1);
+    c.halpha = dconst<S>(p[P_HALPHA]); c.halpha.d[1] = S(0.5);
     c.beta = dconst<S>(p[P_BETA]);    c.beta.d[3] = S(1);
+    c.hbeta = dconst<S>(p[P_HBETA]);  c.hbeta.d[3] = S(0.5);
     c.n = dconst<S>(p[P_N]);          c.n.d[4] = S(1);
     c.ninv2n = dconst<S>(p[P_NINV2N]);
     c.ninv2n.d[4] = S(2) * p[P_NINV2N] * p[P_NINV2N];     // d/dn (-1/(2n)) = 1/(2n^2)
@@ -148,24 +151,26 @@ __device__ __forceinline__ void site_eval(const Geo<S, M>& g, const Cand<V, S>& 
         const V e = dexp2(-(p.aL * delta));
         const V fR = p.D0 * (e * e);
         const V fA = p.twoD0 * e;
+        // zeta = 0 (no other neighbour inside the cutoff, or all at cos = h):
+        // zeta^n = 0 exactly, so b = 1 and db/dzeta * zeta^n-terms vanish
         const bool pos = val(z) > S(0);
         const V zs = dselect(pos, z, vconst<V, S>(S(1)));
-        const V zn = dexp2(p.n * dlog2(zs));
+        const V zn = dselect(pos, dexp2(p.n * dlog2(zs)), vconst<V, S>(S(0)));
         const V onep = S(1) + zn;
-        V b = dexp2(p.ninv2n * dlog2(onep));
-        V bp = S(-0.5) * (b * zn) * drcp(zs * onep);
-        b = dselect(pos, b, vconst<V, S>(S(1)));
-        bp = dselect(pos, bp, vconst<V, S>(S(0)));
-        const V diff = fR - b * fA;
+        const V b = dexp2(p.ninv2n * dlog2(onep));
+        const V bfA = b * fA;
+        const V diff = fR - bfA;
         usum = usum + g.fc[j] * diff;
-        D[j] = S(0.5) * (g.fcp[j] * diff + (g.fc[j] * p.alpha) * (b * fA - S(2) * fR));
-        cc[j] = -(p.beta * (g.fc[j] * (fA * bp)));
+        // D = 1/2 [f_C' (f_R - b f_A) + f_C alpha (b f_A - 2 f_R)]
+        D[j] = g.hfcp[j] * diff + (p.halpha * g.fc[j]) * (bfA - S(2) * fR);
+        // c~ = -beta f_C f_A db/dzeta with db/dzeta = -b zeta^n / (2 zeta (1 + zeta^n))
+        cc[j] = (p.hbeta * g.fc[j]) * (bfA * zn) * drcp(zs * onep);
     }
     U = S(0.5) * usum;
-    V Vx[MM], Vy[MM], Vz[MM], A[MM], Pp[MM];
+    V Vx[MM], Vy[MM], Vz[MM], Pp[MM];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        Vx[j] = Vy[j] = Vz[j] = A[j] = Pp[j] = vconst<V, S>(S(0));
+        Vx[j] = Vy[j] = Vz[j] = Pp[j] = vconst<V, S>(S(0));
     }
     {
         int pidx = 0;
@@ -179,17 +184,16 @@ __device__ __forceinline__ void site_eval(const Geo<S, M>& g, const Cand<V, S>& 
                 const V q = (cc[j] * g.fc[k] + cc[k] * g.fc[j]) * t;
                 Vx[j] = Vx[j] + q * g.ux[k]; Vy[j] = Vy[j] + q * g.uy[k]; Vz[j] = Vz[j] + q * g.uz[k];
                 Vx[k] = Vx[k] + q * g.ux[j]; Vy[k] = Vy[k] + q * g.uy[j]; Vz[k] = Vz[k] + q * g.uz[j];
-                const V qc = q * c;
-                A[j] = A[j] - qc;
-                A[k] = A[k] - qc;
                 Pp[j] = Pp[j] + cc[k] * t2;
                 Pp[k] = Pp[k] + cc[j] * t2;
             }
         }
     }
+    // sum_k q_jk cos_jk = u_j . V_j, so the radial part needs no per-pair term
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        const V rad = D[j] + (S(0.5) * g.fcp[j]) * Pp[j] + A[j] * g.rinv[j];
+        const V uv = g.ux[j] * Vx[j] + g.uy[j] * Vy[j] + g.uz[j] * Vz[j];
+        const V rad = D[j] + g.hfcp[j] * Pp[j] - uv * g.rinv[j];
         Gx[j] = rad * g.ux[j] + Vx[j] * g.rinv[j];
         Gy[j] = rad * g.uy[j] + Vy[j] * g.rinv[j];
         Gz[j] = rad * g.uz[j] + Vz[j] * g.rinv[j];

@@ -1,0 +1,316 @@
+"""GPU parity at the full workload sizes.
+
+* GA fitness batch: 200 candidates x 100 strained 64-atom diamond cells, in the
+  launch shape the benchmark uses, against the oracle on sampled candidates.
+* Uneven batching: 300 structures of 8-512 atoms (strained diamond supercells,
+  the same with vacancies, random packings with coordination up to 12) and
+  500 candidates.  The oracle's brute-force neighbour search takes about a
+  minute for the whole set, so at full size it checks sampled structures one
+  at a time; the fitness reduction over all 300 is checked by properties
+  (batched = plain bit for bit in float64, float32 against float64, Z against
+  the Sec. III.B formula applied on the host to the same call's E, W and F).
+  An 18-structure subset covering every kind and size class is compared with
+  the oracle's fitness and gradient directly.
+* Fitness gradient over the uneven structures (population 64): central finite
+  differences of the float64 fitness, h = 1e-6.
+* 64,000-atom force call: forces and per-atom virials of sampled atoms against
+  the oracle's cluster evaluation; sum rules (net force, sum of per-atom
+  virials = virial, J = sum_i W_i v_i) over all atoms.
+
+Tolerances (GPU vs oracle) as in test_gpu_parity: float64 path 1e-10 relative
+to the quantity's scale; float32 arithmetic 1e-6 eV/atom energy, 1e-4 eV/A
+force, 1e-5 eV/atom virial.
+"""
+import os
+import shutil
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import tersoff as T
+from oracle.neighbors import neighbor_list
+
+pytestmark = pytest.mark.gpu
+
+R1, R2 = 2.8, 3.2
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TUNED = os.path.join(ROOT, "paper_1909_11474_amd", "tuned_shapes.txt")
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_11474_amd import api as A
+    return A
+
+
+@pytest.fixture(scope="module")
+def uneven():
+    return W.config3()
+
+
+@pytest.fixture(scope="module")
+def uneven_set(api, uneven):
+    ts = api.from_structures(uneven.structs)
+    yield ts
+    ts.close()
+
+
+def sample_structures(structs):
+    """Every kind at its smallest and largest size, plus a few in between."""
+    sizes = structs.sizes()
+    kinds = np.asarray(structs.kinds)
+    pick = set()
+    for k in np.unique(kinds):
+        idx = np.nonzero(kinds == k)[0]
+        pick.add(int(idx[np.argmin(sizes[idx])]))
+        pick.add(int(idx[np.argmax(sizes[idx])]))
+        pick.update(int(v) for v in idx[:: max(1, len(idx) // 4)])
+    return sorted(pick)
+
+
+def rel_err(a, b, floor):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), floor)
+
+
+# ---------------------------------------------------------------------------
+# GA fitness batch at full size, benchmark launch shape
+# ---------------------------------------------------------------------------
+
+def test_ga_batch_full_size_in_benchmark_shape(api, tmp_path):
+    wl = W.config2()
+    refs = T.reference_data(wl.structs, wl.hidden_x, R1, R2)
+    ts = api.from_structures(wl.structs)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    P = wl.population.shape[0]
+    cache = tmp_path / "shapes.txt"
+    shutil.copy(TUNED, cache)
+    ts.autotune(P, "fp32", str(cache))
+    Z32 = ts.fitness(wl.population, precision="fp32").cpu().numpy()
+    Z64 = ts.fitness(wl.population, precision="fp64").cpu().numpy()
+    idx = [0, 41, 118, 199]
+    top = T.topology(wl.structs, R2)
+    Zo = T.fitness(wl.structs, wl.population[idx], refs, topology=top)
+    assert rel_err(Z64[idx], Zo, 1e-12) <= 1e-10
+    assert rel_err(Z32[idx], Zo, 1e-12) <= 1e-5
+    # every candidate: float32 against float64 of the same call
+    assert rel_err(Z32, Z64, 1e-12) <= 1e-5
+    ts.close()
+
+
+# ---------------------------------------------------------------------------
+# Uneven batching
+# ---------------------------------------------------------------------------
+
+def test_uneven_neighbors_sampled(api, uneven, uneven_set):
+    s = uneven.structs
+    i, j, sh = uneven_set.neighbors()
+    off = s.offset
+    st_of = np.searchsorted(off, i, side="right") - 1
+    for k in sample_structures(s):
+        print("structure", k, s.kinds[k], s.sizes()[k], flush=True)
+        m = st_of == k
+        got = sorted(zip((i[m] - off[k]).tolist(), (j[m] - off[k]).tolist(), *np.asarray(sh[m]).T.tolist()))
+        pos, cell = s.structure(k)
+        oi, oj, osh = neighbor_list(pos, cell, R2)
+        assert got == sorted(zip(oi.tolist(), oj.tolist(), *osh.T.tolist())), k
+    # whole set: every entry has its reverse and lies inside the cutoff
+    st = uneven_set.stats()
+    assert st["n_bonds"] == len(i) and st["max_coordination"] <= 16
+    fwd = set(zip(i.tolist(), j.tolist(), *np.asarray(sh).T.tolist()))
+    assert all((b, a, -x, -y, -z) in fwd for a, b, x, y, z in fwd)
+    cells = s.cell[st_of]
+    d = s.pos[j] - s.pos[i] + np.einsum("bk,bkl->bl", np.asarray(sh, float), cells)
+    r = np.sqrt((d * d).sum(1))
+    assert r.max() < R2 and r.min() > 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_uneven_eval_sampled(api, uneven, uneven_set, precision):
+    s = uneven.structs
+    X = uneven.population[:2]
+    out = uneven_set.tersoff_eval(X, precision=precision, atom_virial=True)
+    E, F, Wv, Wi = (out[k].cpu().numpy() for k in ("E", "F", "W", "Wi"))
+    sizes = s.sizes()
+    for k in sample_structures(s):
+        pos, cell = s.structure(k)
+        a0, a1 = s.offset[k], s.offset[k + 1]
+        for c, x in enumerate(X):
+            print("structure", k, s.kinds[k], sizes[k], "candidate", c, precision, flush=True)
+            ref = T.evaluate(pos, cell, x, R1, R2, atom_virial=True)
+            if precision == "fp64":
+                assert abs(E[c, k] - ref["E"][0]) <= 1e-10 * max(abs(ref["E"][0]), 1e-2)
+                assert np.abs(F[c, a0:a1] - ref["F"]).max() <= 1e-10 * max(np.abs(ref["F"]).max(), 1e-12) + 1e-12
+                assert np.abs(Wv[c, k] - ref["W6"][0]).max() <= 1e-10 * max(np.abs(ref["W6"]).max(), 1e-2)
+                assert np.abs(Wi[c, a0:a1] - ref["Wi"]).max() <= 1e-10 * max(np.abs(ref["Wi"]).max(), 1e-2)
+            else:
+                assert abs(E[c, k] - ref["E"][0]) / sizes[k] <= 1e-6
+                assert np.abs(F[c, a0:a1] - ref["F"]).max() <= 1e-4
+                assert np.abs(Wv[c, k] - ref["W6"][0]).max() / sizes[k] <= 1e-5
+                assert np.abs(Wi[c, a0:a1] - ref["Wi"]).max() <= 1e-4
+
+
+def synthetic_references(structs, seed):
+    """Reference data of plausible magnitude for property checks (not a fit target)."""
+    g = rng(seed)
+    e = g.normal(-4.3, 0.2, size=structs.n_struct)
+    w = g.normal(0.0, 0.3, size=(structs.n_struct, 6))
+    f = g.normal(0.0, 0.5, size=(structs.n_atoms, 3))
+    return e, w, f
+
+
+def host_fitness(E, Wv, F, e_ref, w_ref, f_ref, sizes, weights):
+    """Sec. III.B relative RMSE fitness from per-structure energies/virials and forces."""
+    n = sizes.astype(float)
+    Ze = np.sqrt(((E / n - e_ref) ** 2).sum() / (e_ref ** 2).sum())
+    Zv = np.sqrt(((Wv / n[:, None] - w_ref) ** 2).sum() / (w_ref ** 2).sum())
+    Zf = np.sqrt(((F - f_ref) ** 2).sum() / (f_ref ** 2).sum())
+    return weights[0] * Ze + weights[1] * Zv + weights[2] * Zf, Ze, Zv, Zf
+
+
+def test_uneven_fitness_full_size_properties(api, uneven, uneven_set):
+    s = uneven.structs
+    e, w, f = synthetic_references(s, 11)
+    uneven_set.attach_reference(e, w, f)
+    X = uneven.population
+    weights = (1.0, 0.8, 1.2)
+    Zb = uneven_set.fitness(X, weights, "fp64", "batched").cpu().numpy()
+    Zp = uneven_set.fitness(X, weights, "fp64", "plain").cpu().numpy()
+    assert np.array_equal(Zb, Zp)
+    Z32 = uneven_set.fitness(X, weights, "fp32", "batched").cpu().numpy()
+    assert rel_err(Z32, Zb, 1e-12) <= 1e-5
+    idx = [0, 250, 499]
+    out = uneven_set.tersoff_eval(X[idx], precision="fp64")
+    for r, c in enumerate(idx):
+        h = host_fitness(out["E"][r].cpu().numpy(), out["W"][r].cpu().numpy(),
+                         out["F"][r].cpu().numpy(), e, w, f, s.sizes(), weights)
+        assert np.abs(Zb[c] - np.array(h)).max() <= 1e-10 * abs(h[0])
+
+
+def uneven_subset(uneven):
+    return uneven.structs.subset(sample_structures(uneven.structs))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_uneven_subset_fitness_vs_oracle(api, uneven, precision):
+    sub = uneven_subset(uneven)
+    refs = T.reference_data(sub, uneven.hidden_x, R1, R2)
+    ts = api.from_structures(sub)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    X = uneven.population[:40]
+    weights = (1.0, 0.5, 2.0)
+    Zb = ts.fitness(X, weights, precision, "batched").cpu().numpy()
+    Zp = ts.fitness(X, weights, precision, "plain").cpu().numpy()
+    idx = [0, 17, 39]
+    Zo = T.fitness(sub, X[idx], refs, weights, topology=T.topology(sub, R2))
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    assert rel_err(Zb[idx], Zo, 1e-12) <= tol
+    if precision == "fp64":
+        assert np.array_equal(Zb, Zp)
+    else:
+        assert rel_err(Zb, Zp, 1e-12) <= 1e-6
+    ts.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_uneven_subset_gradient_vs_oracle(api, uneven, precision):
+    sub = uneven_subset(uneven)
+    refs = T.reference_data(sub, uneven.hidden_x, R1, R2)
+    ts = api.from_structures(sub)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    X = uneven.population[:3]
+    weights = (1.0, 0.7, 1.3)
+    Z, G = (t.cpu().numpy() for t in ts.fitness_grad(X, weights, precision))
+    Zo, Go = T.fitness_grad(sub, X, refs, weights, topology=T.topology(sub, R2))
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    for c in range(len(X)):
+        assert np.abs(G[c] - Go[c]).max() <= tol * np.abs(Go[c]).max(), c
+    assert rel_err(Z, Zo, 1e-12) <= (1e-10 if precision == "fp64" else 1e-5)
+    ts.close()
+
+
+def test_gradient_matches_finite_differences_full_size(api, uneven_set):
+    """d(fitness)/d(parameters) over all 300 uneven structures against central
+    differences of the float64 fitness (h = 1e-6 in each parameter)."""
+    wl = W.config4()
+    e, w, f = synthetic_references(wl.structs, 12)
+    uneven_set.attach_reference(e, w, f)
+    weights = (1.0, 0.6, 1.4)
+    X = wl.population[:4]
+    Z, G = (t.cpu().numpy() for t in uneven_set.fitness_grad(X, weights, "fp64"))
+    h = 1e-6
+    for c in range(len(X)):
+        fd = np.zeros(6)
+        for k in range(6):
+            Xp = np.repeat(X[c:c + 1], 2, axis=0)
+            Xp[0, k] += h
+            Xp[1, k] -= h
+            Zk = uneven_set.fitness(Xp, weights, "fp64").cpu().numpy()[:, 0]
+            fd[k] = (Zk[0] - Zk[1]) / (2 * h)
+        print("candidate", c, "grad", G[c], "fd", fd, flush=True)
+        assert np.abs(G[c] - fd).max() <= 1e-5 * np.abs(fd).max()
+    # float32 arithmetic against float64, same call shape
+    _, G32 = (t.cpu().numpy() for t in uneven_set.fitness_grad(X, weights, "fp32"))
+    for c in range(len(X)):
+        assert np.abs(G32[c] - G[c]).max() <= 1e-4 * np.abs(G[c]).max()
+
+
+# ---------------------------------------------------------------------------
+# 64,000-atom force call
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def big(api):
+    wl = W.config5()
+    ts = api.from_structures(wl.structs)
+    out = {p: {k: v.cpu().numpy() for k, v in
+               ts.tersoff_eval(wl.population, precision=p, atom_virial=True,
+                               velocities=wl.velocities).items()}
+           for p in ("fp64", "fp32")}
+    st = ts.stats()
+    ts.close()
+    return wl, out, st
+
+
+def test_force_call_64k_sampled_atoms(big):
+    wl, out, st = big
+    assert st["n_atoms"] == 64000 and st["n_bonds"] == 4 * 64000
+    pos, cell = wl.structs.structure(0)
+    atoms = sorted(rng(21).choice(pos.shape[0], size=24, replace=False).tolist())
+    ref = T.local_forces(pos, cell, wl.population[0], atoms, R1, R2)
+    F64, W64 = out["fp64"]["F"][0], out["fp64"]["Wi"][0]
+    F32, W32 = out["fp32"]["F"][0], out["fp32"]["Wi"][0]
+    sF = np.abs(ref["F"]).max()
+    assert np.abs(F64[atoms] - ref["F"]).max() <= 1e-10 * sF + 1e-12
+    assert np.abs(W64[atoms] - ref["Wi"]).max() <= 1e-10 * max(np.abs(ref["Wi"]).max(), 1e-2)
+    assert np.abs(F32[atoms] - ref["F"]).max() <= 1e-4
+    assert np.abs(W32[atoms] - ref["Wi"]).max() <= 1e-4
+
+
+def test_force_call_64k_sum_rules(big):
+    wl, out, _ = big
+    N = wl.structs.n_atoms
+    o64, o32 = out["fp64"], out["fp32"]
+    F = o64["F"][0]
+    assert np.abs(F.sum(axis=0)).max() <= 1e-9 * np.abs(F).max() * np.sqrt(N)
+    Wsum = o64["Wi"][0].sum(axis=0)                       # [3, 3]
+    W6 = o64["W"][0, 0]                                   # xx yy zz yz zx xy
+    full = np.array([Wsum[0, 0], Wsum[1, 1], Wsum[2, 2],
+                     0.5 * (Wsum[1, 2] + Wsum[2, 1]), 0.5 * (Wsum[2, 0] + Wsum[0, 2]),
+                     0.5 * (Wsum[0, 1] + Wsum[1, 0])])
+    assert np.abs(full - W6).max() <= 1e-9 * np.abs(W6).max()
+    assert np.abs(Wsum - Wsum.T).max() <= 1e-8 * np.abs(Wsum).max()
+    J_host = np.einsum("imn,in->m", o64["Wi"][0], wl.velocities)
+    assert np.abs(o64["J"][0] - J_host).max() <= 1e-10 * np.abs(J_host).max()
+    # float32 arithmetic against float64
+    assert abs(o32["E"][0, 0] - o64["E"][0, 0]) / N <= 1e-6
+    assert np.abs(o32["F"][0] - F).max() <= 1e-4
+    assert np.abs(o32["W"][0, 0] - W6).max() / N <= 1e-5
+    assert np.abs(o32["J"][0] - o64["J"][0]).max() <= 1e-5 * np.abs(o64["J"][0]).max() + 1e-6

@@ -40,7 +40,7 @@ constexpr int kMaxBatched = 512;   // largest structure of the batched kernel
 constexpr int kNVFit = 8;          // partial sums per slot: E, W6, |F - F*|^2
 constexpr int kNVEval = 16;        // E, W6, |F-F*|^2, J3, unused
 constexpr int kNVGrad = 8;         // dZ/dx (6), unused (2)
-constexpr int kNParam = 16;        // per-candidate decoded parameter record
+constexpr int kNParam = 20;        // per-candidate decoded parameter record
 
 // Decoded parameter record (float or double), filled per work item in LDS.
 enum ParamIndex {
@@ -55,7 +55,13 @@ enum ParamIndex {
     P_H = 9,
     P_VALID = 10,   // 1 if the candidate is inside the potential's domain
     P_HALPHA = 11,  // alpha / 2
-    P_HBETA = 12    // beta / 2
+    P_HBETA = 12,   // beta / 2
+    // float records: low parts (value - float(value)) of the parameters the
+    // float64 energy terms use; zero in double records
+    P_ALLO = 13,
+    P_D0LO = 14,
+    P_NLO = 15,
+    P_NINV2NLO = 16
 };
 
 struct Item {       // one (structure, candidate range) work item of the batched kernel
@@ -101,6 +107,51 @@ __device__ __forceinline__ float drcp(float x) { return __builtin_amdgcn_rcpf(x)
 __device__ __forceinline__ double dexp2(double x) { return exp2(x); }
 __device__ __forceinline__ double dlog2(double x) { return log2(x); }
 __device__ __forceinline__ double drcp(double x) { return 1.0 / x; }
+
+// float64 2^y and log2(x) for the energy terms of the float path: about 1e-12
+// relative error, finite normal arguments only.
+//   2^y: y = k + f with k = rint(y), |f| <= 1/2; 2^f = e^(f ln 2) by its Taylor
+//   series to degree 9 (remainder (ln2/2)^10 / 10! < 7e-12).
+//   log2(x): x = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s),
+//   s = (m - 1)/(m + 1), |s| <= 0.172, series to s^13 (remainder < 2e-12).
+__device__ __forceinline__ double exp2_acc(double y) {
+    const double k = __builtin_rint(y);
+    const double f = y - k;
+    double p = 1.01780860092397e-07;            // (ln 2)^i / i!, i = 9 .. 0
+    p = p * f + 1.321548679014431e-06;
+    p = p * f + 1.5252733804059841e-05;
+    p = p * f + 0.0001540353039338161;
+    p = p * f + 0.0013333558146428443;
+    p = p * f + 0.009618129107628477;
+    p = p * f + 0.05550410866482158;
+    p = p * f + 0.24022650695910072;
+    p = p * f + 0.6931471805599453;
+    p = p * f + 1.0;
+    return __builtin_amdgcn_ldexp(p, (int)k);
+}
+
+__device__ __forceinline__ double log2_acc(double x) {
+    double m = __builtin_amdgcn_frexp_mant(x);      // [1/2, 1)
+    int e = __builtin_amdgcn_frexp_exp(x);
+    if (m < 0.70710678118654752) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double a = m + 1.0;
+    double q = __builtin_amdgcn_rcp(a);             // refined twice: error ~ (2^-26)^4
+    q = q * (2.0 - a * q);
+    q = q * (2.0 - a * q);
+    const double s = (m - 1.0) * q;
+    const double s2 = s * s;
+    double t = 1.0 / 13.0;                          // 1/(2i+1), i = 6 .. 0
+    t = t * s2 + 1.0 / 11.0;
+    t = t * s2 + 1.0 / 9.0;
+    t = t * s2 + 1.0 / 7.0;
+    t = t * s2 + 1.0 / 5.0;
+    t = t * s2 + 1.0 / 3.0;
+    t = t * s2 + 1.0;
+    return (double)e + (2.0 * s * t) * 1.4426950408889634;     // ln m / ln 2
+}
 
 template <typename S>
 struct Consts;

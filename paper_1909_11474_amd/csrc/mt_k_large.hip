@@ -1,16 +1,29 @@
 // Instantiates the two-pass large-structure kernels of mt_kernels.h.
+#include <type_traits>
+
 #include "mt_kernels.h"
 
 namespace mt {
 
+template <typename S, bool E64>
+static hipError_t launch_large_site(int mc, dim3 g, dim3 b, hipStream_t st, const BArgs<S>& A,
+                                    const LArgs& L) {
+    switch (mc) {
+        case 4: hipLaunchKernelGGL((k_large_site<S, 4, E64>), g, b, 0, st, A, L); break;
+        case 16: hipLaunchKernelGGL((k_large_site<S, 16, E64>), g, b, 0, st, A, L); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+}
+
 template <typename S>
 static hipError_t launch_large_pair(int mc, int mode, dim3 g, dim3 b, hipStream_t st,
                                     const BArgs<S>& A, const LArgs& L) {
-    switch (mc) {
-        case 4: hipLaunchKernelGGL((k_large_site<S, 4>), g, b, 0, st, A, L); break;
-        case 16: hipLaunchKernelGGL((k_large_site<S, 16>), g, b, 0, st, A, L); break;
-        default: return hipErrorInvalidValue;
-    }
+    // float64 energy terms matter only for float arithmetic in the energy mode
+    const hipError_t e = (std::is_same<S, float>::value && mode == MODE_EVAL)
+                             ? launch_large_site<S, std::is_same<S, float>::value>(mc, g, b, st, A, L)
+                             : launch_large_site<S, false>(mc, g, b, st, A, L);
+    if (e != hipSuccess) return e;
     if (mode == MODE_FIT) hipLaunchKernelGGL((k_large_gather<S, MODE_FIT>), g, b, 0, st, A, L);
     else hipLaunchKernelGGL((k_large_gather<S, MODE_EVAL>), g, b, 0, st, A, L);
     return hipGetLastError();

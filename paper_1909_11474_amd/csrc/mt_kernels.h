@@ -66,6 +66,11 @@ __device__ __forceinline__ void decode_record(const double* __restrict__ x, S* _
     o[P_VALID] = ok ? S(1) : S(0);
     o[P_HALPHA] = (S)(0.5 * al);
     o[P_HBETA] = (S)(0.5 * be);
+    const double aL = al * 1.4426950408889634, ni = -1.0 / (2.0 * n);
+    o[P_ALLO] = (S)(aL - (double)(S)aL);
+    o[P_D0LO] = (S)(D0 - (double)(S)D0);
+    o[P_NLO] = (S)(n - (double)(S)n);
+    o[P_NINV2NLO] = (S)(ni - (double)(S)ni);
 }
 
 template <typename S>
@@ -207,9 +212,9 @@ __device__ __forceinline__ void run_batched(const BArgs<S>& A, const Item& it, c
         const int c = it.c0 + clv;
         Cand<S, S> p;
         load_cand(pbuf + kNParam * clv, p);
-        S U;
+        double U;
         S Gx[MM], Gy[MM], Gz[MM];
-        site_eval<S, S, M>(g, p, U, Gx, Gy, Gz);
+        site_eval<S, S, M, MODE == MODE_EVAL>(g, p, U, Gx, Gy, Gz);
 #pragma unroll
         for (int m = 0; m < M; ++m) xb[x.own + m * x.g] = Vec4<S>{Gx[m], Gy[m], Gz[m], S(0)};
         exchange_sync(x.block_sync);
@@ -473,7 +478,7 @@ struct LArgs {
     void* gbuf;                // [chunk][3][nbs] of S
 };
 
-template <typename S, int M>
+template <typename S, int M, bool E64>
 __device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L, int la, int atom,
                                                bool active) {
     const SetDev& d = A.set;
@@ -489,9 +494,9 @@ __device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L
     decode_record<S>(A.x + 6 * (size_t)c, rec);
     Cand<S, S> p;
     load_cand(rec, p);
-    S U;
+    double U;
     S Gx[MM], Gy[MM], Gz[MM];
-    site_eval<S, S, M>(g, p, U, Gx, Gy, Gz);
+    site_eval<S, S, M, E64>(g, p, U, Gx, Gy, Gz);
     S* gb = reinterpret_cast<S*>(L.gbuf) + (size_t)blockIdx.y * 3 * nbs;
     if (active) {
 #pragma unroll
@@ -525,7 +530,8 @@ __device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L
         A.partial[((size_t)c * d.nslots + slot) * A.nv + vidx] = sum;
 }
 
-template <typename S, int MC>
+// E64: float64 energy terms (the float path's energy/force/virial mode).
+template <typename S, int MC, bool E64>
 __global__ __launch_bounds__(256) void k_large_site(BArgs<S> A, LArgs L) {
     const SetDev& d = A.set;
     const int a0 = d.st_off[L.s], Ns = d.st_off[L.s + 1] - a0;
@@ -536,7 +542,7 @@ __global__ __launch_bounds__(256) void k_large_site(BArgs<S> A, LArgs L) {
     const int Mw = wave_max_int(Mi);
     if (Mw < 0) return;
     dispatch_m<ClassLo<MC>::value, MC>(Mw, [&](auto mv) {
-        run_large_site<S, decltype(mv)::value>(A, L, la, atom, active);
+        run_large_site<S, decltype(mv)::value, E64>(A, L, la, atom, active);
     });
 }
 

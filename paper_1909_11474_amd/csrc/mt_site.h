@@ -24,6 +24,8 @@
 // S is the geometry type.  The code is written once for all of them.
 #pragma once
 
+#include <type_traits>
+
 #include "mt_common.h"
 
 namespace mt {
@@ -91,13 +93,22 @@ template <typename V, typename S>
 struct Cand {
     V aL, r0hi, r0lo, D0, twoD0, halpha, beta, hbeta, n, ninv2n, h;
     S valid;
+    S aLlo, D0lo, nlo, ninv2nlo;     // low parts for the float64 energy terms
 };
+
+// Type of the site energy: float64 for the float path (its energy terms are
+// evaluated in float64), the value type otherwise.
+template <typename V>
+struct EnergyOf { using type = V; };
+template <>
+struct EnergyOf<float> { using type = double; };
 
 template <typename S>
 __device__ __forceinline__ void load_cand(const S* __restrict__ p, Cand<S, S>& c) {
     c.aL = p[P_AL]; c.r0hi = p[P_R0HI]; c.r0lo = p[P_R0LO]; c.D0 = p[P_D0]; c.twoD0 = p[P_2D0];
     c.halpha = p[P_HALPHA]; c.beta = p[P_BETA]; c.hbeta = p[P_HBETA];
     c.n = p[P_N]; c.ninv2n = p[P_NINV2N]; c.h = p[P_H];
+    c.aLlo = p[P_ALLO]; c.D0lo = p[P_D0LO]; c.nlo = p[P_NLO]; c.ninv2nlo = p[P_NINV2NLO];
     c.valid = p[P_VALID];
 }
 
@@ -120,8 +131,9 @@ __device__ __forceinline__ void load_cand(const S* __restrict__ p, Cand<Dual<S>,
     c.valid = p[P_VALID];
 }
 
-template <typename V, typename S, int M>
-__device__ __forceinline__ void site_eval(const Geo<S, M>& g, const Cand<V, S>& p, V& U,
+template <typename V, typename S, int M, bool Energy64 = false>
+__device__ __forceinline__ void site_eval(const Geo<S, M>& g, const Cand<V, S>& p,
+                                          typename EnergyOf<V>::type& U,
                                           V* __restrict__ Gx, V* __restrict__ Gy,
                                           V* __restrict__ Gz) {
     constexpr int MM = M > 0 ? M : 1;
@@ -142,31 +154,52 @@ __device__ __forceinline__ void site_eval(const Geo<S, M>& g, const Cand<V, S>& 
             }
         }
     }
+    // Energy64 (float path): the pair terms and the bond order of the energy
+    // are evaluated in float64.  In float32 the representation error of f_R
+    // and b f_A (up to ~15 eV each for parameters inside the fitting box)
+    // alone reaches 1e-6 eV per bond.  Their float32 roundings feed the
+    // gradient either way.
+    constexpr bool kE64 = Energy64 && std::is_same<V, float>::value;
     V cc[MM], D[MM];
     V usum = vconst<V, S>(S(0));
+    double usum64 = 0.0;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         const V z = zeta[j] * p.beta;
-        const V delta = (g.rhi[j] - p.r0hi) + (g.rlo[j] - p.r0lo);
-        const V e = dexp2(-(p.aL * delta));
-        const V fR = p.D0 * (e * e);
-        const V fA = p.twoD0 * e;
         // zeta = 0 (no other neighbour inside the cutoff, or all at cos = h):
         // zeta^n = 0 exactly, so b = 1 and db/dzeta * zeta^n-terms vanish
         const bool pos = val(z) > S(0);
         const V zs = dselect(pos, z, vconst<V, S>(S(1)));
-        const V zn = dselect(pos, dexp2(p.n * dlog2(zs)), vconst<V, S>(S(0)));
+        V e, zn, b;
+        if constexpr (kE64) {
+            const double dl = ((double)g.rhi[j] - (double)p.r0hi) + ((double)g.rlo[j] - (double)p.r0lo);
+            const double e64 = exp2_acc(-(((double)p.aL + (double)p.aLlo) * dl));
+            const double zn64 =
+                pos ? exp2_acc(((double)p.n + (double)p.nlo) * log2_acc((double)zs)) : 0.0;
+            const double b64 = exp2_acc(((double)p.ninv2n + (double)p.ninv2nlo) * log2_acc(1.0 + zn64));
+            const double D0 = (double)p.D0 + (double)p.D0lo;
+            usum64 += (double)g.fc[j] * (D0 * e64 * (e64 - 2.0 * b64));
+            e = (float)e64;
+            zn = (float)zn64;
+            b = (float)b64;
+        } else {
+            const V delta = (g.rhi[j] - p.r0hi) + (g.rlo[j] - p.r0lo);
+            e = dexp2(-(p.aL * delta));
+            zn = dselect(pos, dexp2(p.n * dlog2(zs)), vconst<V, S>(S(0)));
+            b = dexp2(p.ninv2n * dlog2(S(1) + zn));
+        }
         const V onep = S(1) + zn;
-        const V b = dexp2(p.ninv2n * dlog2(onep));
+        const V fR = p.D0 * (e * e);
+        const V fA = p.twoD0 * e;
+        const V diff = fR - b * fA;           // one rounding (fused multiply-add)
         const V bfA = b * fA;
-        const V diff = fR - bfA;
-        usum = usum + g.fc[j] * diff;
+        if constexpr (!kE64) usum = usum + g.fc[j] * diff;
         // D = 1/2 [f_C' (f_R - b f_A) + f_C alpha (b f_A - 2 f_R)]
         D[j] = g.hfcp[j] * diff + (p.halpha * g.fc[j]) * (bfA - S(2) * fR);
         // c~ = -beta f_C f_A db/dzeta with db/dzeta = -b zeta^n / (2 zeta (1 + zeta^n))
         cc[j] = (p.hbeta * g.fc[j]) * (bfA * zn) * drcp(zs * onep);
     }
-    U = S(0.5) * usum;
+    if constexpr (kE64) U = 0.5 * usum64; else U = S(0.5) * usum;
     V Vx[MM], Vy[MM], Vz[MM], Pp[MM];
 #pragma unroll
     for (int j = 0; j < M; ++j) {

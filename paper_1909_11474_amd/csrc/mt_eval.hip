@@ -73,12 +73,64 @@ __device__ __forceinline__ void struct_sums(const FinArgs& F, int c, int s, doub
     }
 }
 
+// Structures with more partial-sum slots than this (more than 2,048 atoms)
+// are summed by the whole block; smaller ones by one thread each.
+constexpr int kCoopSlots = 32;
+
+// Block-wide slot sums of structure s (all threads call; the result is valid
+// in every thread).  Each thread adds a fixed strided subset of the slots,
+// then a fixed tree adds the threads: the order depends only on the sizes.
+__device__ void coop_struct_sums(const FinArgs& F, int c, int s, double* e, double* w6, double* rf,
+                                 double* j3, double (*sh)[256]) {
+    const SetDev& d = F.set;
+    double a[11];
+    for (int k = 0; k < 11; ++k) a[k] = 0;
+    const int nv = F.nv >= 11 ? 11 : 8;
+    for (int sl = d.st_slot[s] + threadIdx.x; sl < d.st_slot[s + 1]; sl += blockDim.x) {
+        const double* p = F.partial + ((size_t)c * d.nslots + sl) * F.nv;
+        for (int k = 0; k < nv; ++k) a[k] += p[k];
+    }
+    __syncthreads();
+    for (int k = 0; k < 11; ++k) sh[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < 11; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    *e = sh[0][0];
+    for (int k = 0; k < 6; ++k) w6[k] = sh[1 + k][0];
+    *rf = sh[7][0];
+    for (int k = 0; k < 3; ++k) j3[k] = sh[8 + k][0];
+    __syncthreads();
+}
+
+__device__ __forceinline__ bool coop_struct(const SetDev& d, int s) {
+    return d.st_slot[s + 1] - d.st_slot[s] > kCoopSlots;
+}
+
 __global__ __launch_bounds__(256) void k_finalize_fit(FinArgs F) {
-    __shared__ double sh[3][256];
+    __shared__ double sh[11][256];
     const int c = blockIdx.x;
     const SetDev& d = F.set;
     double acc[3] = {0, 0, 0};
+    for (int s = 0; s < d.S; ++s) {
+        if (!coop_struct(d, s)) continue;
+        double e, w6[6], rf, j3[3];
+        coop_struct_sums(F, c, s, &e, w6, &rf, j3, sh);
+        if (threadIdx.x == 0) {
+            const double n = (double)(d.st_off[s + 1] - d.st_off[s]);
+            const double de = e / n - F.eref[s];
+            acc[0] += de * de;
+            for (int k = 0; k < 6; ++k) {
+                const double dw = w6[k] / n - F.wref[6 * s + k];
+                acc[1] += dw * dw;
+            }
+            acc[2] += rf;
+        }
+    }
     for (int s = threadIdx.x; s < d.S; s += blockDim.x) {
+        if (coop_struct(d, s)) continue;
         double e, w6[6], rf, j3[3];
         struct_sums(F, c, s, &e, w6, &rf, j3);
         const double n = (double)(d.st_off[s + 1] - d.st_off[s]);
@@ -150,13 +202,25 @@ __global__ __launch_bounds__(256) void k_finalize_grad(FinArgs F, double* dZdx) 
 }
 
 __global__ __launch_bounds__(256) void k_finalize_eval(FinArgs F) {
-    __shared__ double sh[3][256];
+    __shared__ double sh[11][256];
     const int c = blockIdx.x;
     const SetDev& d = F.set;
     const bool ok = cand_valid(F.x, c);
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
     double jacc[3] = {0, 0, 0};
+    for (int s = 0; s < d.S; ++s) {
+        if (!coop_struct(d, s)) continue;
+        double e, w6[6], rf, j3[3];
+        coop_struct_sums(F, c, s, &e, w6, &rf, j3, sh);
+        if (threadIdx.x == 0) {
+            if (F.energy) F.energy[(size_t)c * d.S + s] = ok ? e : nan;
+            if (F.virial)
+                for (int k = 0; k < 6; ++k) F.virial[((size_t)c * d.S + s) * 6 + k] = ok ? w6[k] : nan;
+            for (int k = 0; k < 3; ++k) jacc[k] += j3[k];
+        }
+    }
     for (int s = threadIdx.x; s < d.S; s += blockDim.x) {
+        if (coop_struct(d, s)) continue;
         double e, w6[6], rf, j3[3];
         struct_sums(F, c, s, &e, w6, &rf, j3);
         if (F.energy) F.energy[(size_t)c * d.S + s] = ok ? e : nan;
@@ -290,14 +354,15 @@ static int tile_for(const LaunchCfg& cfg, int P, int R, bool plain) {
     return std::min(tile, ((P + R - 1) / R) * R);
 }
 
-// Block size for structure s: the requested one, or the largest smaller
-// multiple of the padded size (at least 64 threads) whose LDS fits the
-// device; 0 when a single replica does not fit.
+// Block size for structure s: the requested one when its LDS fits the device
+// (replicas that do not fill the block leave whole wavefronts idle), else the
+// largest smaller multiple of 64 threads, at least the padded size, that fits;
+// 0 when a single replica does not fit.  Keeping the requested size keeps
+// every structure of a class in one launch.
 static int block_for(const mt_set* set, int s, const LaunchCfg& cfg, int P, int fam, bool plain) {
     const int npad = set->h_npad[s];
-    const int step = std::max(64, npad);
-    int block = plain ? step : (cfg.block / step) * step;
-    for (; block >= step; block -= step) {
+    const int least = std::max(64, npad);
+    for (int block = plain ? least : cfg.block; block >= least; block -= 64) {
         const int R = block / npad;
         if (item_lds(set, s, block, fam, std::min(tile_for(cfg, P, R, plain), P)) <= set->lds_max)
             return block;

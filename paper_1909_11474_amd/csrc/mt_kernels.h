@@ -331,14 +331,15 @@ __device__ __forceinline__ void batched_item(const BArgs<S>& A, const Item& it, 
     });
 }
 
-// Occupancy target per class: the M <= 4 class fits 4 wavefronts per SIMD.
-template <typename S, int MC>
+// Occupancy target per class: the float fitness kernel of the M <= 4 class
+// fits 4 wavefronts per SIMD (128 registers).
+template <typename S, int MODE, int MC>
 struct WavesPerEU {
-    static constexpr int value = (MC <= 4 && sizeof(S) == 4) ? 4 : 1;
+    static constexpr int value = (MC <= 4 && sizeof(S) == 4 && MODE == MODE_FIT) ? 4 : 1;
 };
 
 template <typename S, int MODE, int MC>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S, MC>::value)))
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S, MODE, MC>::value)))
 void k_batched(BArgs<S> A) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int b0 = A.bin_off[blockIdx.x], b1 = A.bin_off[blockIdx.x + 1];
@@ -353,7 +354,7 @@ void k_batched(BArgs<S> A) {
 // that evaluates the item A.items[0].  The same device code as k_batched,
 // under a kernel name of its own so that profiles keep the two apart.
 template <typename S, int MODE, int MC>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S, MC>::value)))
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S, MODE, MC>::value)))
 void k_plain(BArgs<S> A) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
     batched_item<S, MODE, MC>(A, A.items[0], lds_raw);

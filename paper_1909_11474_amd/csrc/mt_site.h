@@ -131,12 +131,31 @@ __device__ __forceinline__ void load_cand(const S* __restrict__ p, Cand<Dual<S>,
     c.valid = p[P_VALID];
 }
 
+// Make the compiler treat the values as changed here (no instruction is
+// emitted): expressions of them after this point are recomputed, not reused.
+template <typename S, int N>
+__device__ __forceinline__ void opaque(S (&a)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) asm volatile("" : "+v"(a[i]));
+}
+
+// Largest coordination whose backward sweep runs over unordered bond pairs.
+constexpr int kPairwiseMax = 8;
+
 template <typename V, typename S, int M, bool Energy64 = false>
-__device__ __forceinline__ void site_eval(const Geo<S, M>& g, const Cand<V, S>& p,
+__device__ __forceinline__ void site_eval(Geo<S, M> g, const Cand<V, S>& p,
                                           typename EnergyOf<V>::type& U,
                                           V* __restrict__ Gx, V* __restrict__ Gy,
                                           V* __restrict__ Gz) {
     constexpr int MM = M > 0 ? M : 1;
+    if constexpr (!Geo<S, M>::kCache && M > 1) {
+        // cos(theta) is not cached for larger M: keep the compiler from
+        // hoisting the M (M - 1) / 2 values out of the candidate loop (they
+        // would not fit in registers and go to scratch)
+        opaque(g.ux);
+        opaque(g.uy);
+        opaque(g.uz);
+    }
     V zeta[MM];
 #pragma unroll
     for (int j = 0; j < M; ++j) zeta[j] = vconst<V, S>(S(0));
@@ -198,8 +217,42 @@ __device__ __forceinline__ void site_eval(const Geo<S, M>& g, const Cand<V, S>& 
         D[j] = g.hfcp[j] * diff + (p.halpha * g.fc[j]) * (bfA - S(2) * fR);
         // c~ = -beta f_C f_A db/dzeta with db/dzeta = -b zeta^n / (2 zeta (1 + zeta^n))
         cc[j] = (p.hbeta * g.fc[j]) * (bfA * zn) * drcp(zs * onep);
+        // large M: keep the scheduler from interleaving all M bonds' chains
+        // (about ten live values each)
+        if constexpr (M > kPairwiseMax) __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (kE64) U = 0.5 * usum64; else U = S(0.5) * usum;
+    if constexpr (M > kPairwiseMax) {
+        // Large M: one bond at a time, visiting each pair from both ends.
+        // About 1.5x the backward arithmetic of the pairwise sweep below, but
+        // only four running sums are live instead of 4 M, which keeps the
+        // kernel out of scratch spills.  The barrier stops the compiler from
+        // keeping the forward sweep's per-pair terms (about 2 M^2 values)
+        // alive for reuse here.
+        opaque(g.ux);
+        opaque(g.uy);
+        opaque(g.uz);
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            V vx = vconst<V, S>(S(0)), vy = vx, vz = vx, pp = vx;
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                if (k == j) continue;
+                const S c = g.ux[j] * g.ux[k] + g.uy[j] * g.uy[k] + g.uz[j] * g.uz[k];
+                const V t = c - p.h;
+                const V q = (cc[j] * g.fc[k] + cc[k] * g.fc[j]) * t;
+                vx = vx + q * g.ux[k]; vy = vy + q * g.uy[k]; vz = vz + q * g.uz[k];
+                pp = pp + (cc[k] * t) * t;
+            }
+            const V uv = g.ux[j] * vx + g.uy[j] * vy + g.uz[j] * vz;
+            const V rad = D[j] + g.hfcp[j] * pp - uv * g.rinv[j];
+            Gx[j] = rad * g.ux[j] + vx * g.rinv[j];
+            Gy[j] = rad * g.uy[j] + vy * g.rinv[j];
+            Gz[j] = rad * g.uz[j] + vz * g.rinv[j];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        return;
+    }
     V Vx[MM], Vy[MM], Vz[MM], Pp[MM];
 #pragma unroll
     for (int j = 0; j < M; ++j) {

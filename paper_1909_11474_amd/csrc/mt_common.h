@@ -164,103 +164,109 @@ struct Consts<double> {
     static constexpr double ln2 = 0.693147180559945309;
 };
 
-// Forward-mode derivative with respect to the six parameters.
-template <typename S>
+// Forward-mode derivative with respect to K of the six parameters (which
+// ones is set where the parameter record is seeded).
+template <typename S, int K = 6>
 struct Dual {
     S v;
-    S d[6];
+    S d[K];
 };
 
-template <typename S>
-__device__ __forceinline__ Dual<S> dconst(S v) {
-    Dual<S> r;
+template <typename T>
+struct DualOf { static constexpr int tangents = 0; };
+template <typename S, int K>
+struct DualOf<Dual<S, K>> { static constexpr int tangents = K; };
+
+template <typename S, int K>
+__device__ __forceinline__ Dual<S, K> dconst(S v) {
+    Dual<S, K> r;
     r.v = v;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) r.d[k] = S(0);
+    for (int k = 0; k < K; ++k) r.d[k] = S(0);
     return r;
 }
 
 template <typename S> __device__ __forceinline__ S val(S a) { return a; }
-template <typename S> __device__ __forceinline__ S val(const Dual<S>& a) { return a.v; }
+template <typename S, int K> __device__ __forceinline__ S val(const Dual<S, K>& a) { return a.v; }
 
-template <typename S>
-__device__ __forceinline__ Dual<S> operator+(const Dual<S>& a, const Dual<S>& b) {
-    Dual<S> r; r.v = a.v + b.v;
+template <typename S, int K>
+__device__ __forceinline__ Dual<S, K> operator+(const Dual<S, K>& a, const Dual<S, K>& b) {
+    Dual<S, K> r; r.v = a.v + b.v;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) r.d[k] = a.d[k] + b.d[k];
+    for (int k = 0; k < K; ++k) r.d[k] = a.d[k] + b.d[k];
     return r;
 }
-template <typename S>
-__device__ __forceinline__ Dual<S> operator-(const Dual<S>& a, const Dual<S>& b) {
-    Dual<S> r; r.v = a.v - b.v;
+template <typename S, int K>
+__device__ __forceinline__ Dual<S, K> operator-(const Dual<S, K>& a, const Dual<S, K>& b) {
+    Dual<S, K> r; r.v = a.v - b.v;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) r.d[k] = a.d[k] - b.d[k];
+    for (int k = 0; k < K; ++k) r.d[k] = a.d[k] - b.d[k];
     return r;
 }
-template <typename S>
-__device__ __forceinline__ Dual<S> operator-(const Dual<S>& a) {
-    Dual<S> r; r.v = -a.v;
+template <typename S, int K>
+__device__ __forceinline__ Dual<S, K> operator-(const Dual<S, K>& a) {
+    Dual<S, K> r; r.v = -a.v;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) r.d[k] = -a.d[k];
+    for (int k = 0; k < K; ++k) r.d[k] = -a.d[k];
     return r;
 }
-template <typename S>
-__device__ __forceinline__ Dual<S> operator*(const Dual<S>& a, const Dual<S>& b) {
-    Dual<S> r; r.v = a.v * b.v;
+template <typename S, int K>
+__device__ __forceinline__ Dual<S, K> operator*(const Dual<S, K>& a, const Dual<S, K>& b) {
+    Dual<S, K> r; r.v = a.v * b.v;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+    for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
     return r;
 }
-template <typename S>
-__device__ __forceinline__ Dual<S> operator*(const Dual<S>& a, S b) {
-    Dual<S> r; r.v = a.v * b;
+template <typename S, int K>
+__device__ __forceinline__ Dual<S, K> operator*(const Dual<S, K>& a, S b) {
+    Dual<S, K> r; r.v = a.v * b;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) r.d[k] = a.d[k] * b;
+    for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b;
     return r;
 }
-template <typename S>
-__device__ __forceinline__ Dual<S> operator*(S b, const Dual<S>& a) { return a * b; }
-template <typename S>
-__device__ __forceinline__ Dual<S> operator+(const Dual<S>& a, S b) {
-    Dual<S> r = a; r.v += b; return r;
+template <typename S, int K>
+__device__ __forceinline__ Dual<S, K> operator*(S b, const Dual<S, K>& a) { return a * b; }
+template <typename S, int K>
+__device__ __forceinline__ Dual<S, K> operator+(const Dual<S, K>& a, S b) {
+    Dual<S, K> r = a; r.v += b; return r;
 }
-template <typename S>
-__device__ __forceinline__ Dual<S> operator+(S b, const Dual<S>& a) { return a + b; }
-template <typename S>
-__device__ __forceinline__ Dual<S> operator-(const Dual<S>& a, S b) {
-    Dual<S> r = a; r.v -= b; return r;
+template <typename S, int K>
+__device__ __forceinline__ Dual<S, K> operator+(S b, const Dual<S, K>& a) { return a + b; }
+template <typename S, int K>
+__device__ __forceinline__ Dual<S, K> operator-(const Dual<S, K>& a, S b) {
+    Dual<S, K> r = a; r.v -= b; return r;
 }
-template <typename S>
-__device__ __forceinline__ Dual<S> operator-(S b, const Dual<S>& a) { return (-a) + b; }
-template <typename S>
-__device__ __forceinline__ Dual<S> dexp2(const Dual<S>& a) {
-    Dual<S> r; r.v = dexp2(a.v);
+template <typename S, int K>
+__device__ __forceinline__ Dual<S, K> operator-(S b, const Dual<S, K>& a) { return (-a) + b; }
+template <typename S, int K>
+__device__ __forceinline__ Dual<S, K> dexp2(const Dual<S, K>& a) {
+    Dual<S, K> r; r.v = dexp2(a.v);
     const S g = r.v * Consts<S>::ln2;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) r.d[k] = g * a.d[k];
+    for (int k = 0; k < K; ++k) r.d[k] = g * a.d[k];
     return r;
 }
-template <typename S>
-__device__ __forceinline__ Dual<S> dlog2(const Dual<S>& a) {
-    Dual<S> r; r.v = dlog2(a.v);
+template <typename S, int K>
+__device__ __forceinline__ Dual<S, K> dlog2(const Dual<S, K>& a) {
+    Dual<S, K> r; r.v = dlog2(a.v);
     const S g = drcp(a.v * Consts<S>::ln2);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) r.d[k] = g * a.d[k];
+    for (int k = 0; k < K; ++k) r.d[k] = g * a.d[k];
     return r;
 }
-template <typename S>
-__device__ __forceinline__ Dual<S> drcp(const Dual<S>& a) {
-    Dual<S> r; r.v = drcp(a.v);
+template <typename S, int K>
+__device__ __forceinline__ Dual<S, K> drcp(const Dual<S, K>& a) {
+    Dual<S, K> r; r.v = drcp(a.v);
     const S g = -r.v * r.v;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) r.d[k] = g * a.d[k];
+    for (int k = 0; k < K; ++k) r.d[k] = g * a.d[k];
     return r;
 }
-template <typename S>
-__device__ __forceinline__ Dual<S> dselect(bool c, const Dual<S>& a, const Dual<S>& b) {
-    Dual<S> r; r.v = c ? a.v : b.v;
+template <typename S, int K>
+__device__ __forceinline__ Dual<S, K> dselect(bool c, const Dual<S, K>& a, const Dual<S, K>& b) {
+    Dual<S, K> r; r.v = c ? a.v : b.v;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) r.d[k] = c ? a.d[k] : b.d[k];
+    for (int k = 0; k < K; ++k) r.d[k] = c ? a.d[k] : b.d[k];
     return r;
 }
 template <typename S>
@@ -268,7 +274,7 @@ __device__ __forceinline__ S dselect(bool c, S a, S b) { return c ? a : b; }
 
 template <typename V, typename S>
 __device__ __forceinline__ V vconst(S v) {
-    if constexpr (sizeof(V) == sizeof(S)) return v; else return dconst<S>(v);
+    if constexpr (sizeof(V) == sizeof(S)) return v; else return dconst<S, DualOf<V>::tangents>(v);
 }
 
 // ---------------------------------------------------------------------------

@@ -369,7 +369,20 @@ void k_plain(BArgs<S> A) {
 // C_s = w_v/(N_s Z_v Q_v) times the symmetric matrix of virial residuals (off
 // diagonals halved).  These follow from dF_i/dx = -d/dx dE/dr_i and
 // dW/dx = -sum r_ij (x) dG_ij/dx.
+//
+// Per candidate: a plain pass gives the force residuals a_i, shared through
+// LDS; then dual passes over K of the six parameters at a time contract each
+// G_ij' with delta_ij as soon as the site routine emits it, so no bond
+// gradient derivative is held across the exchange.
 // ---------------------------------------------------------------------------
+
+// Tangents per dual pass: all six in one pass for small coordination, three
+// (two passes) where six would not fit in registers.
+template <typename S, int M>
+struct AdjointTangents {
+    static constexpr int value = (M <= 4 && sizeof(S) == 4) ? 6 : 3;
+};
+
 template <typename S, int M>
 __device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, const ItemCtx& x,
                                             unsigned char* __restrict__ lds) {
@@ -381,6 +394,7 @@ __device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, c
     Geo<S, M> g;
     g.load(geom_of<S>(d), N, x.atom, x.active);
     constexpr int MM = M > 0 ? M : 1;
+    constexpr int K = AdjointTangents<S, M>::value;
     int rv[MM], jl[MM];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
@@ -394,24 +408,27 @@ __device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, c
     for (int step = 0; step < x.steps; ++step) {
         const int cl = x.q + step * x.R;
         const bool group_ok = cl < it.nc;
-        const bool cok = x.active && group_ok;
         const int clv = group_ok ? cl : 0;
         const int c = it.c0 + clv;
-        Cand<Dual<S>, S> p;
-        load_cand(pbuf + kNParam * clv, p);
-        Dual<S> U;
-        Dual<S> Gx[MM], Gy[MM], Gz[MM];
-        site_eval<Dual<S>, S, M>(g, p, U, Gx, Gy, Gz);
-#pragma unroll
-        for (int m = 0; m < M; ++m) xb[x.own + m * x.g] = Vec4<S>{Gx[m].v, Gy[m].v, Gz[m].v, S(0)};
-        exchange_sync(x.block_sync);
+        const S* prec = pbuf + kNParam * clv;
+        // plain pass: force residual of this atom
         S ax = S(0), ay = S(0), az = S(0);
+        {
+            Cand<S, S> pp;
+            load_cand(prec, pp);
+            double U0;
+            S Gx[MM], Gy[MM], Gz[MM];
+            site_eval<S, S, M>(g, pp, U0, Gx, Gy, Gz);
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const Vec4<S> r = xb[rv[m]];
-            ax += Gx[m].v - r.x;
-            ay += Gy[m].v - r.y;
-            az += Gz[m].v - r.z;
+            for (int m = 0; m < M; ++m) xb[x.own + m * x.g] = Vec4<S>{Gx[m], Gy[m], Gz[m], S(0)};
+            exchange_sync(x.block_sync);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const Vec4<S> r = xb[rv[m]];
+                ax += Gx[m] - r.x;
+                ay += Gy[m] - r.y;
+                az += Gz[m] - r.z;
+            }
         }
         ax -= frx; ay -= fry; az -= frz;
         ab[x.la] = Vec4<S>{ax, ay, az, S(0)};
@@ -421,17 +438,37 @@ __device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, c
         const S cxx = (S)cf[2], cyy = (S)cf[3], czz = (S)cf[4];
         const S cyz = (S)cf[5], czx = (S)cf[6], cxy = (S)cf[7];
         S phi[6];
+        // dual passes
+        auto pass = [&](auto base_c) {
+            constexpr int Base = decltype(base_c)::value;
+            Cand<Dual<S, K>, S> p;
+            load_cand<Base>(prec, p);
+            Dual<S, K> U;
+            site_eval_sink<Dual<S, K>, S, M, false, true, true>(
+                g, p, U, [&](int m, const Dual<S, K>& gx, const Dual<S, K>& gy, const Dual<S, K>& gz) {
+                    // a fresh read in every pass (a reused one would stay live across passes)
+                    int jm = jl[m];
+                    asm volatile("" : "+v"(jm));
+                    const Vec4<S> aj = ab[jm];
+                    const S dx = g.rhi[m] * g.ux[m], dy = g.rhi[m] * g.uy[m], dz = g.rhi[m] * g.uz[m];
+                    const S ex = kf * (aj.x - ax) + cxx * dx + cxy * dy + czx * dz;
+                    const S ey = kf * (aj.y - ay) + cxy * dx + cyy * dy + cyz * dz;
+                    const S ez = kf * (aj.z - az) + czx * dx + cyz * dy + czz * dz;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) phi[k] = ke * U.d[k];
+                    for (int t = 0; t < K; ++t) phi[Base + t] -= gx.d[t] * ex + gy.d[t] * ey + gz.d[t] * ez;
+                });
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const Vec4<S> aj = ab[jl[m]];
-            const S dx = g.rhi[m] * g.ux[m], dy = g.rhi[m] * g.uy[m], dz = g.rhi[m] * g.uz[m];
-            const S ex = kf * (aj.x - ax) + cxx * dx + cxy * dy + czx * dz;
-            const S ey = kf * (aj.y - ay) + cxy * dx + cyy * dy + cyz * dz;
-            const S ez = kf * (aj.z - az) + czx * dx + cyz * dy + czz * dz;
+            for (int t = 0; t < K; ++t) phi[Base + t] += ke * U.d[t];
+        };
 #pragma unroll
-            for (int k = 0; k < 6; ++k) phi[k] -= Gx[m].d[k] * ex + Gy[m].d[k] * ey + Gz[m].d[k] * ez;
+        for (int k = 0; k < 6; ++k) phi[k] = S(0);
+        pass(std::integral_constant<int, 0>{});
+        if constexpr (K <= 3) pass(std::integral_constant<int, K>{});
+        if constexpr (K <= 2) pass(std::integral_constant<int, 2 * K>{});
+        if constexpr (K == 1) {
+            pass(std::integral_constant<int, 3>{});
+            pass(std::integral_constant<int, 4>{});
+            pass(std::integral_constant<int, 5>{});
         }
         exchange_sync(x.block_sync);
         double v[8];

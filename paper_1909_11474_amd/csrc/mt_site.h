@@ -112,22 +112,34 @@ __device__ __forceinline__ void load_cand(const S* __restrict__ p, Cand<S, S>& c
     c.valid = p[P_VALID];
 }
 
-// Seeds the six parameter directions D0, alpha, r0, beta, n, h.
-template <typename S>
-__device__ __forceinline__ void load_cand(const S* __restrict__ p, Cand<Dual<S>, S>& c) {
+// Seeds K parameter directions, parameters Base .. Base + K - 1 of
+// (D0, alpha, r0, beta, n, h).
+template <int Base, typename S, int K>
+__device__ __forceinline__ void load_cand(const S* __restrict__ p, Cand<Dual<S, K>, S>& c) {
     const S log2e = S(1.4426950408889634);
-    c.aL = dconst<S>(p[P_AL]);        c.aL.d[1] = log2e;
-    c.r0hi = dconst<S>(p[P_R0HI]);    c.r0hi.d[2] = S(1);
-    c.r0lo = dconst<S>(p[P_R0LO]);
-    c.D0 = dconst<S>(p[P_D0]);        c.D0.d[0] = S(1);
-    c.twoD0 = dconst<S>(p[P_2D0]);    c.twoD0.d[0] = S(2);
-    c.halpha = dconst<S>(p[P_HALPHA]); c.halpha.d[1] = S(0.5);
-    c.beta = dconst<S>(p[P_BETA]);    c.beta.d[3] = S(1);
-    c.hbeta = dconst<S>(p[P_HBETA]);  c.hbeta.d[3] = S(0.5);
-    c.n = dconst<S>(p[P_N]);          c.n.d[4] = S(1);
-    c.ninv2n = dconst<S>(p[P_NINV2N]);
-    c.ninv2n.d[4] = S(2) * p[P_NINV2N] * p[P_NINV2N];     // d/dn (-1/(2n)) = 1/(2n^2)
-    c.h = dconst<S>(p[P_H]);          c.h.d[5] = S(1);
+    c.aL = dconst<S, K>(p[P_AL]);
+    c.r0hi = dconst<S, K>(p[P_R0HI]);
+    c.r0lo = dconst<S, K>(p[P_R0LO]);
+    c.D0 = dconst<S, K>(p[P_D0]);
+    c.twoD0 = dconst<S, K>(p[P_2D0]);
+    c.halpha = dconst<S, K>(p[P_HALPHA]);
+    c.beta = dconst<S, K>(p[P_BETA]);
+    c.hbeta = dconst<S, K>(p[P_HBETA]);
+    c.n = dconst<S, K>(p[P_N]);
+    c.ninv2n = dconst<S, K>(p[P_NINV2N]);
+    c.h = dconst<S, K>(p[P_H]);
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        switch (Base + t) {
+            case 0: c.D0.d[t] = S(1); c.twoD0.d[t] = S(2); break;
+            case 1: c.aL.d[t] = log2e; c.halpha.d[t] = S(0.5); break;
+            case 2: c.r0hi.d[t] = S(1); break;
+            case 3: c.beta.d[t] = S(1); c.hbeta.d[t] = S(0.5); break;
+            // d/dn (-1/(2n)) = 1/(2n^2)
+            case 4: c.n.d[t] = S(1); c.ninv2n.d[t] = S(2) * p[P_NINV2N] * p[P_NINV2N]; break;
+            case 5: c.h.d[t] = S(1); break;
+        }
+    }
     c.valid = p[P_VALID];
 }
 
@@ -142,13 +154,25 @@ __device__ __forceinline__ void opaque(S (&a)[N]) {
 // Largest coordination whose backward sweep runs over unordered bond pairs.
 constexpr int kPairwiseMax = 8;
 
-template <typename V, typename S, int M, bool Energy64 = false>
-__device__ __forceinline__ void site_eval(Geo<S, M> g, const Cand<V, S>& p,
-                                          typename EnergyOf<V>::type& U,
-                                          V* __restrict__ Gx, V* __restrict__ Gy,
-                                          V* __restrict__ Gz) {
+// The site routine.  It hands each bond gradient G_j to sink(j, Gx, Gy, Gz);
+// PerBond selects the one-bond-at-a-time backward sweep (for large M, or for
+// dual numbers, whose per-bond state is K + 1 times larger), which emits G_j
+// as soon as it is complete.
+// Fresh: treat the geometry as new, so that nothing computed from it by an
+// earlier call in the same loop iteration is kept alive for reuse (repeated
+// dual passes over the same site would otherwise hold every shared primal
+// value across passes).  The barriers act on the caller's geometry in place
+// (they change no value), so no second copy of it becomes live.
+template <typename V, typename S, int M, bool Energy64, bool PerBond, bool Fresh = false,
+          typename Sink>
+__device__ __forceinline__ void site_eval_sink(Geo<S, M>& g, const Cand<V, S>& p,
+                                               typename EnergyOf<V>::type& U, Sink&& sink) {
     constexpr int MM = M > 0 ? M : 1;
-    if constexpr (!Geo<S, M>::kCache && M > 1) {
+    if constexpr (Fresh && M > 0) {
+        opaque(g.rhi); opaque(g.rlo); opaque(g.rinv); opaque(g.fc); opaque(g.hfcp);
+        if constexpr (Geo<S, M>::kCache && Geo<S, M>::NP > 0) opaque(g.cs);
+    }
+    if constexpr ((Fresh || !Geo<S, M>::kCache) && M > 1) {
         // cos(theta) is not cached for larger M: keep the compiler from
         // hoisting the M (M - 1) / 2 values out of the candidate loop (they
         // would not fit in registers and go to scratch)
@@ -217,13 +241,13 @@ __device__ __forceinline__ void site_eval(Geo<S, M> g, const Cand<V, S>& p,
         D[j] = g.hfcp[j] * diff + (p.halpha * g.fc[j]) * (bfA - S(2) * fR);
         // c~ = -beta f_C f_A db/dzeta with db/dzeta = -b zeta^n / (2 zeta (1 + zeta^n))
         cc[j] = (p.hbeta * g.fc[j]) * (bfA * zn) * drcp(zs * onep);
-        // large M: keep the scheduler from interleaving all M bonds' chains
+        // per-bond sweep: keep the scheduler from interleaving all M bonds' chains
         // (about ten live values each)
-        if constexpr (M > kPairwiseMax) __builtin_amdgcn_sched_barrier(0);
+        if constexpr (PerBond) __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (kE64) U = 0.5 * usum64; else U = S(0.5) * usum;
-    if constexpr (M > kPairwiseMax) {
-        // Large M: one bond at a time, visiting each pair from both ends.
+    if constexpr (PerBond) {
+        // One bond at a time, visiting each pair from both ends.
         // About 1.5x the backward arithmetic of the pairwise sweep below, but
         // only four running sums are live instead of 4 M, which keeps the
         // kernel out of scratch spills.  The barrier stops the compiler from
@@ -246,9 +270,8 @@ __device__ __forceinline__ void site_eval(Geo<S, M> g, const Cand<V, S>& p,
             }
             const V uv = g.ux[j] * vx + g.uy[j] * vy + g.uz[j] * vz;
             const V rad = D[j] + g.hfcp[j] * pp - uv * g.rinv[j];
-            Gx[j] = rad * g.ux[j] + vx * g.rinv[j];
-            Gy[j] = rad * g.uy[j] + vy * g.rinv[j];
-            Gz[j] = rad * g.uz[j] + vz * g.rinv[j];
+            sink(j, rad * g.ux[j] + vx * g.rinv[j], rad * g.uy[j] + vy * g.rinv[j],
+                 rad * g.uz[j] + vz * g.rinv[j]);
             __builtin_amdgcn_sched_barrier(0);
         }
         return;
@@ -280,10 +303,23 @@ __device__ __forceinline__ void site_eval(Geo<S, M> g, const Cand<V, S>& p,
     for (int j = 0; j < M; ++j) {
         const V uv = g.ux[j] * Vx[j] + g.uy[j] * Vy[j] + g.uz[j] * Vz[j];
         const V rad = D[j] + g.hfcp[j] * Pp[j] - uv * g.rinv[j];
-        Gx[j] = rad * g.ux[j] + Vx[j] * g.rinv[j];
-        Gy[j] = rad * g.uy[j] + Vy[j] * g.rinv[j];
-        Gz[j] = rad * g.uz[j] + Vz[j] * g.rinv[j];
+        sink(j, rad * g.ux[j] + Vx[j] * g.rinv[j], rad * g.uy[j] + Vy[j] * g.rinv[j],
+             rad * g.uz[j] + Vz[j] * g.rinv[j]);
     }
+}
+
+// The site routine with the bond gradients returned in arrays.
+template <typename V, typename S, int M, bool Energy64 = false>
+__device__ __forceinline__ void site_eval(Geo<S, M>& g, const Cand<V, S>& p,
+                                          typename EnergyOf<V>::type& U,
+                                          V* __restrict__ Gx, V* __restrict__ Gy,
+                                          V* __restrict__ Gz) {
+    site_eval_sink<V, S, M, Energy64, (M > kPairwiseMax)>(
+        g, p, U, [&](int j, const V& x, const V& y, const V& z) {
+            Gx[j] = x;
+            Gy[j] = y;
+            Gz[j] = z;
+        });
 }
 
 // Cross-lane exchanges of a double, 32 bits at a time.

@@ -55,6 +55,7 @@ struct FinArgs {
     double* Z;                 // [P][4]
     double* coef;              // [P][S][8] or null (gradient coefficients)
     double* energy; double* virial; double* heat;
+    int coop;                  // 1 if some structure has more than kCoopSlots slots
 };
 
 __device__ __forceinline__ void struct_sums(const FinArgs& F, int c, int s, double* e, double* w6,
@@ -114,7 +115,7 @@ __global__ __launch_bounds__(256) void k_finalize_fit(FinArgs F) {
     const int c = blockIdx.x;
     const SetDev& d = F.set;
     double acc[3] = {0, 0, 0};
-    for (int s = 0; s < d.S; ++s) {
+    for (int s = 0; F.coop && s < d.S; ++s) {
         if (!coop_struct(d, s)) continue;
         double e, w6[6], rf, j3[3];
         coop_struct_sums(F, c, s, &e, w6, &rf, j3, sh);
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(256) void k_finalize_fit(FinArgs F) {
         }
     }
     for (int s = threadIdx.x; s < d.S; s += blockDim.x) {
-        if (coop_struct(d, s)) continue;
+        if (F.coop && coop_struct(d, s)) continue;
         double e, w6[6], rf, j3[3];
         struct_sums(F, c, s, &e, w6, &rf, j3);
         const double n = (double)(d.st_off[s + 1] - d.st_off[s]);
@@ -208,7 +209,7 @@ __global__ __launch_bounds__(256) void k_finalize_eval(FinArgs F) {
     const bool ok = cand_valid(F.x, c);
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
     double jacc[3] = {0, 0, 0};
-    for (int s = 0; s < d.S; ++s) {
+    for (int s = 0; F.coop && s < d.S; ++s) {
         if (!coop_struct(d, s)) continue;
         double e, w6[6], rf, j3[3];
         coop_struct_sums(F, c, s, &e, w6, &rf, j3, sh);
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(256) void k_finalize_eval(FinArgs F) {
         }
     }
     for (int s = threadIdx.x; s < d.S; s += blockDim.x) {
-        if (coop_struct(d, s)) continue;
+        if (F.coop && coop_struct(d, s)) continue;
         double e, w6[6], rf, j3[3];
         struct_sums(F, c, s, &e, w6, &rf, j3);
         if (F.energy) F.energy[(size_t)c * d.S + s] = ok ? e : nan;
@@ -260,6 +261,9 @@ FinArgs make_fin(mt_set* set, int nv, const double* partial) {
     F.wref = set->wref.as<double>();
     F.Qe = set->Q[0]; F.Qv = set->Q[1]; F.Qf = set->Q[2];
     F.x = set->cur_x;
+    F.coop = 0;
+    for (int s = 0; s < set->S; ++s)
+        if (set->h_slot[s + 1] - set->h_slot[s] > kCoopSlots) F.coop = 1;
     return F;
 }
 

@@ -156,6 +156,43 @@ __global__ __launch_bounds__(256) void k_finalize_fit(FinArgs F) {
     }
 }
 
+// Z for sets without block-wide structures: one wavefront per candidate (four
+// per block), lanes over structures, then a fixed xor butterfly, after which
+// every lane holds the same sums.
+__global__ __launch_bounds__(256) void k_finalize_fit_wave(FinArgs F, int P) {
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= P) return;
+    const SetDev& d = F.set;
+    double acc[3] = {0, 0, 0};
+    for (int s = lane; s < d.S; s += 64) {
+        double e, w6[6], rf, j3[3];
+        struct_sums(F, c, s, &e, w6, &rf, j3);
+        const double n = (double)(d.st_off[s + 1] - d.st_off[s]);
+        const double de = e / n - F.eref[s];
+        acc[0] += de * de;
+        for (int k = 0; k < 6; ++k) {
+            const double dw = w6[k] / n - F.wref[6 * s + k];
+            acc[1] += dw * dw;
+        }
+        acc[2] += rf;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[k] += __shfl_xor(acc[k], o, 64);
+    if (lane == 0) {
+        const bool ok = cand_valid(F.x, c);
+        const double Ze = sqrt(acc[0] / F.Qe), Zv = sqrt(acc[1] / F.Qv), Zf = sqrt(acc[2] / F.Qf);
+        const double Z = F.we * Ze + F.wv * Zv + F.wf * Zf;
+        const double nan = __longlong_as_double(0x7ff8000000000000ll);
+        F.Z[4 * c + 0] = ok ? Z : nan;
+        F.Z[4 * c + 1] = ok ? Ze : nan;
+        F.Z[4 * c + 2] = ok ? Zv : nan;
+        F.Z[4 * c + 3] = ok ? Zf : nan;
+    }
+}
+
 // Gradient coefficients per (candidate, structure), from the forward partials
 // and Z: k_e, k_f, and C_s (xx yy zz yz zx xy, off-diagonals halved).
 __global__ __launch_bounds__(256) void k_grad_coef(FinArgs F) {
@@ -615,7 +652,10 @@ int launch_finalize_fit(mt_set* set, int P, const double* w, double* Z, hipStrea
     FinArgs F = make_fin(set, kNVFit, set->partial.as<double>());
     F.we = w[0]; F.wv = w[1]; F.wf = w[2];
     F.Z = Z;
-    hipLaunchKernelGGL(k_finalize_fit, dim3(P), dim3(256), 0, st, F);
+    if (F.coop)
+        hipLaunchKernelGGL(k_finalize_fit, dim3(P), dim3(256), 0, st, F);
+    else
+        hipLaunchKernelGGL(k_finalize_fit_wave, dim3((P + 3) / 4), dim3(256), 0, st, F, P);
     HIPCHECK(hipGetLastError());
     return MT_OK;
 }

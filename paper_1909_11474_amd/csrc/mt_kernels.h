@@ -161,12 +161,14 @@ __device__ __forceinline__ void exchange_sync(bool block) {
     }
 }
 
-// Store the group sums of v[0..7] into partial[c][slot][off + vidx].
+// Store the group sums of v[0..7] into partial[c][slot][off + vidx].  GF is
+// the group size when known at compile time (0: x.g at run time).
+template <int GF = 0>
 __device__ __forceinline__ void store_group(double* v, const ItemCtx& x, bool group_ok,
                                             double* __restrict__ partial, int nslots, int nv,
                                             int c, int off, int wmask) {
     int vidx;
-    const double sum = group_reduce8(v, x.g, &vidx);
+    const double sum = GF ? group_reduce8_t<(GF ? GF : 64)>(v, &vidx) : group_reduce8(v, x.g, &vidx);
     const int lane = threadIdx.x & 63;
     if (group_ok && (lane & ((x.g >> 3) - 1)) == 0 && ((wmask >> vidx) & 1))
         partial[((size_t)c * nslots + x.slot) * nv + off + vidx] = sum;
@@ -179,7 +181,7 @@ __device__ __forceinline__ size_t lds_param_bytes(int ptile) {
     return ((size_t)ptile * kNParam * sizeof(S) + 31) & ~(size_t)31;
 }
 
-template <typename S, int MODE, int M>
+template <typename S, int MODE, int M, int GF = 0>
 __device__ __forceinline__ void run_batched(const BArgs<S>& A, const Item& it, const ItemCtx& x,
                                             unsigned char* __restrict__ lds) {
     const SetDev& d = A.set;
@@ -216,7 +218,12 @@ __device__ __forceinline__ void run_batched(const BArgs<S>& A, const Item& it, c
         S Gx[MM], Gy[MM], Gz[MM];
         site_eval<S, S, M, MODE == MODE_EVAL>(g, p, U, Gx, Gy, Gz);
 #pragma unroll
-        for (int m = 0; m < M; ++m) xb[x.own + m * x.g] = Vec4<S>{Gx[m], Gy[m], Gz[m], S(0)};
+        for (int m = 0; m < M; ++m) {
+            S* slot = &xb[x.own + m * x.g].x;         // the fourth component is never read
+            slot[0] = Gx[m];
+            slot[1] = Gy[m];
+            slot[2] = Gz[m];
+        }
         exchange_sync(x.block_sync);
         S Fx = S(0), Fy = S(0), Fz = S(0);
         S wi[9];
@@ -254,10 +261,10 @@ __device__ __forceinline__ void run_batched(const BArgs<S>& A, const Item& it, c
         if (MODE == MODE_FIT) {
             const S ax = Fx - frx, ay = Fy - fry, az = Fz - frz;
             v[7] = (double)(ax * ax + ay * ay + az * az);
-            store_group(v, x, group_ok, A.partial, d.nslots, A.nv, c, 0, 0xff);
+            store_group<GF>(v, x, group_ok, A.partial, d.nslots, A.nv, c, 0, 0xff);
         } else {
             v[7] = 0.0;
-            store_group(v, x, group_ok, A.partial, d.nslots, A.nv, c, 0, 0xff);
+            store_group<GF>(v, x, group_ok, A.partial, d.nslots, A.nv, c, 0, 0xff);
             double u[8];
             const S jx = wi[0] * vx + wi[1] * vy + wi[2] * vz;
             const S jy = wi[3] * vx + wi[4] * vy + wi[5] * vz;
@@ -266,7 +273,7 @@ __device__ __forceinline__ void run_batched(const BArgs<S>& A, const Item& it, c
             u[1] = (double)jy;
             u[2] = (double)jz;
             u[3] = u[4] = u[5] = u[6] = u[7] = 0.0;
-            store_group(u, x, group_ok, A.partial, d.nslots, A.nv, c, 8, 0x07);
+            store_group<GF>(u, x, group_ok, A.partial, d.nslots, A.nv, c, 8, 0x07);
             if (cok && A.force) {
                 double* f = A.force + (size_t)c * 3 * N;
                 f[orig] = (double)Fx;
@@ -327,6 +334,15 @@ __device__ __forceinline__ void batched_item(const BArgs<S>& A, const Item& it, 
         return;
     }
     dispatch_m<ClassLo<MC>::value, MC>(Mw, [&](auto mv) {
+        // the float fitness kernel gets a copy with 64-lane groups (structures
+        // of 64 atoms or more) fixed at compile time: the reduction then needs
+        // no branches and no copies around the in-place lane swaps
+        if constexpr (MODE == MODE_FIT && sizeof(S) == 4) {
+            if (x.g == 64) {
+                run_batched<S, MODE, decltype(mv)::value, 64>(A, it, x, lds);
+                return;
+            }
+        }
         run_batched<S, MODE, decltype(mv)::value>(A, it, x, lds);
     });
 }

@@ -1,0 +1,128 @@
+"""GPU edge cases against the oracle: degenerate structures, sizes around the
+wavefront and batching limits, the two-pass fitness path, population extremes.
+
+Tolerances as in test_gpu_parity (float64 1e-10 relative; float32 1e-6
+eV/atom, 1e-4 eV/A, 1e-5 eV/atom; fitness 1e-5 relative).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import tersoff as T
+
+pytestmark = pytest.mark.gpu
+
+R1, R2 = 2.8, 3.2
+BOX = np.eye(3) * 20.0
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_11474_amd import api as A
+    return A
+
+
+def check_eval(ts, s, X, precision):
+    out = ts.tersoff_eval(X, precision=precision, atom_virial=True)
+    E, F, Wv, Wi = (out[k].cpu().numpy() for k in ("E", "F", "W", "Wi"))
+    sizes = s.sizes().astype(float)
+    for c, x in enumerate(X):
+        ref = T.evaluate_set(s, x, R1, R2, atom_virial=True)
+        if precision == "fp64":
+            assert np.abs(E[c] - ref["E"]).max() <= 1e-10 * max(np.abs(ref["E"]).max(), 1e-2)
+            assert np.abs(F[c] - ref["F"]).max() <= 1e-10 * max(np.abs(ref["F"]).max(), 1e-12) + 1e-12
+            assert np.abs(Wv[c] - ref["W6"]).max() <= 1e-10 * max(np.abs(ref["W6"]).max(), 1e-2)
+            assert np.abs(Wi[c] - ref["Wi"]).max() <= 1e-10 * max(np.abs(ref["Wi"]).max(), 1e-2)
+        else:
+            assert np.abs(E[c] / sizes - ref["E"] / sizes).max() <= 1e-6
+            assert np.abs(F[c] - ref["F"]).max() <= 1e-4
+            assert np.abs(Wv[c] / sizes[:, None] - ref["W6"] / sizes[:, None]).max() <= 1e-5
+            assert np.abs(Wi[c] - ref["Wi"]).max() <= 1e-4
+
+
+def degenerate_set():
+    """Isolated atom (no bonds), dimers at 2.35 A and inside the switching zone
+    (single neighbour: zeta = 0, b = 1), bent and straight trimers
+    (cos theta = -1/2 and -1), and a perfect 8-atom diamond cell."""
+    c = np.array([10.0, 10.0, 10.0])
+    tri = c + 2.4 * np.array([[0, 0, 0], [1, 0, 0], [0.5, np.sqrt(3) / 2, 0]])
+    line = c + np.array([[0, 0, 0], [2.3, 0, 0], [4.6, 0, 0]])
+    pos, cell = W.diamond(1, 1, 1)
+    return W.make_set([(c[None], BOX), (c + [[0, 0, 0], [2.35, 0, 0]], BOX),
+                       (c + [[0, 0, 0], [0, 3.0, 0]], BOX), (tri, BOX), (line, BOX), (pos, cell)])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_degenerate_structures(api, precision):
+    s = degenerate_set()
+    ts = api.from_structures(s)
+    st = ts.stats()
+    assert st["n_bonds"] == 0 + 2 + 2 + 6 + 4 + 32
+    X = np.vstack([np.asarray(W.TABLE2_X)[None], W.draw_params(rng(31), 3)])
+    check_eval(ts, s, X, precision)
+    ts.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_sizes_around_one_wavefront(api, precision):
+    """63, 64 and 65 atoms: the last pads to two wavefronts per replica, the
+    second holding one atom; 8 atoms pads to 8 lanes."""
+    g = rng(32)
+    s = W.make_set([W.random_packing(g, n) for n in (63, 64, 65, 8)])
+    ts = api.from_structures(s)
+    check_eval(ts, s, W.draw_params(rng(33), 3), precision)
+    ts.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fitness_across_the_batching_limit(api, precision):
+    """A 512-atom structure (largest batched, 512 lanes per replica) beside a
+    600-atom one (two-pass path) and 64-atom cells; batched = plain in float64."""
+    g = rng(34)
+    big = W.random_packing(g, 600)
+    edge = W.random_packing(g, 512)
+    s = W.make_set([big, edge] + W.strained_diamond_cells(35, 3))
+    hidden = W.draw_params(rng(36), 1)[0]
+    refs = T.reference_data(s, hidden, R1, R2)
+    ts = api.from_structures(s)
+    st = ts.stats()
+    assert st["n_large"] == 1 and st["n_batched"] == 4 and st["max_atoms"] == 600
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    X = W.draw_params(rng(37), 6)
+    Zb = ts.fitness(X, precision=precision).cpu().numpy()
+    Zp = ts.fitness(X, precision=precision, schedule="plain").cpu().numpy()
+    Zo = T.fitness(s, X[[0, 5]], refs, topology=T.topology(s, R2))
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    assert np.abs(Zb[[0, 5]] - Zo).max() <= tol * np.abs(Zo).max()
+    if precision == "fp64":
+        assert np.array_equal(Zb, Zp)
+    from paper_1909_11474_amd import _lib as L
+    with pytest.raises(L.MTError) as e:                 # the adjoint has no two-pass path
+        ts.fitness_grad(X, precision=precision)
+    assert e.value.code == L.MT_EINVAL
+    ts.close()
+
+
+def test_population_extremes_give_identical_candidates(api):
+    """P = 1 and P = 1000 (the same candidates repeated): every candidate's Z
+    is the same bits whatever the population around it."""
+    wl = W.config2(n_struct=6, pop=8)
+    refs = T.reference_data(wl.structs, wl.hidden_x, R1, R2)
+    ts = api.from_structures(wl.structs)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    X = wl.population
+    big = np.tile(X, (125, 1))
+    for precision in ("fp64", "fp32"):
+        Zbig = ts.fitness(big, precision=precision).cpu().numpy()
+        for c in range(len(X)):
+            Z1 = ts.fitness(X[c:c + 1], precision=precision).cpu().numpy()
+            assert np.array_equal(Z1[0], Zbig[c])
+            assert np.array_equal(Zbig[c], Zbig[c + 8 * 124])
+    ts.close()

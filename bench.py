@@ -13,8 +13,9 @@ float32 arithmetic with float64 accumulation; reference data from a hidden
 parameter set evaluated by the library's float64 path.  The same run also
 measures the plain schedule (one launch per candidate and structure), the
 fitness gradient, uneven batching (500 candidates x 300 structures of 8-512
-atoms), the gradient over those structures (64 candidates) and the
-64,000-atom force call, and times the CPU oracle on a bounded sample.  Prints
+atoms), the gradient over those structures (64 candidates), GA generations
+with gradient refinement over them and the 64,000-atom force call, and times
+the CPU oracle on a bounded sample.  Prints
 one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -60,6 +61,8 @@ def parse():
                     help="gradient calls over the uneven structures (0: skip)")
     ap.add_argument("--md-steps", type=int, default=20,
                     help="64,000-atom force calls (0: skip)")
+    ap.add_argument("--ga-generations", type=int, default=10,
+                    help="GA generations with gradient refinement over the uneven set (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-time budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -202,6 +205,36 @@ def uneven_gradient(args, api, torch, W, dev):
     return out
 
 
+def ga_generations(args, api, torch, W, dev):
+    """The host GA (Sec. III.B) on the GPU fitness over the uneven structures,
+    population 64, with projected-gradient refinement of the best 8 each
+    generation: wall time per generation (fitness, sort, refinement with its
+    gradient and trial fitness, selection, crossover, mutation)."""
+    from paper_1909_11474_amd import ga as G
+    wl = W.config4()
+    P = wl.population.shape[0]
+    ts, _, _ = make_set(api, torch, wl)
+    if not args.no_tune:
+        ts.autotune(P, "fp32", args.tune_cache)
+    fit, grad = G.gpu_fitness(ts, precision="fp32")
+    cfg = G.GAConfig(pop=P, n_par=P // 2, n_gen=500, seed=wl.seeds["population"],
+                     refine_top=8, refine_steps=1)
+    ga = G.GA(cfg, fit, grad)
+    ga.step()                                              # warm-up: plans for P and 8
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.ga_generations):
+        rec = ga.step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.ga_generations
+    out = {"workload": wl.name + "; GA with top-8 gradient refinement",
+           "ms_per_generation": dt * 1e3, "generations": args.ga_generations,
+           "best_Z": rec["best"], "population": P}
+    log(f"GA generation with refinement: {dt * 1e3:.3f} ms")
+    ts.close()
+    return out
+
+
 def force_call(args, api, torch, W, dev):
     wl = W.config5()
     s = wl.structs
@@ -317,6 +350,8 @@ def main():
         workloads["uneven_gradient"] = uneven_gradient(args, api, torch, W, dev)
     if args.md_steps > 0:
         workloads["force_call_64k"] = force_call(args, api, torch, W, dev)
+    if args.ga_generations > 0:
+        workloads["ga_refined"] = ga_generations(args, api, torch, W, dev)
 
     line = {
         "metric": "atom·candidate Tersoff force evals/s and fitness-grad evals/s, batched vs plain",

@@ -14,6 +14,13 @@ Definitions used (paper Sec. II):
   A = D0/(S-1) exp(alpha r0 sqrt(2S)),  B = D0 S/(S-1) exp(alpha r0 sqrt(2/S)),
   lambda = alpha sqrt(2S),  mu = alpha sqrt(2/S),  with S fixed to 2      (Sec. II.B, Eqs. 11-14)
 
+Parameter vectors: the minimal potential x = [D0, alpha, r0, beta, n, h]; the
+Tersoff form with its original angular function
+  g^T = gamma (1 + c^2/d^2 - c^2/(d^2 + (cos theta - h)^2))             (Sec. II.A, Eq. 8)
+and a free slope S, x = [D0, alpha, r0, S, gamma, n, c, d, h] (the paper's nine
+parameters A, B, lambda, mu, gamma, n, c, d, h with A, B, lambda, mu written
+through D0, alpha, r0, S as in Eqs. 11-14).
+
 Readings where the paper is silent (listed with the design notes of the
 library): a neighbour entry is an (atom, periodic image) pair and "k != i, j"
 excludes only the entry j itself; the virial is W = -dE/d(strain) (positive under
@@ -37,15 +44,35 @@ S_SLOPE = 2.0            # Pauling slope fixed to 2 in the minimal potential (Se
 VIRIAL6 = ((0, 0), (1, 1), (2, 2), (1, 2), (2, 0), (0, 1))   # xx yy zz yz zx xy
 
 
+def is_full(x) -> bool:
+    """True for the nine-parameter Tersoff form, False for the minimal one."""
+    return len(x) == 9
+
+
 def derived_params(x: torch.Tensor):
-    """(A, B, lambda, mu) from x = [D0, alpha, r0, beta, n, h] (Sec. II.B, Eqs. 11-14)."""
+    """(A, B, lambda, mu) from x (Sec. II.B, Eqs. 11-14); S = 2 for the minimal
+    potential, x[3] for the nine-parameter form."""
     D0, alpha, r0 = x[0], x[1], x[2]
-    S = S_SLOPE
-    A = D0 / (S - 1.0) * torch.exp(alpha * r0 * math.sqrt(2.0 * S))
-    B = D0 * S / (S - 1.0) * torch.exp(alpha * r0 * math.sqrt(2.0 / S))
-    lam = alpha * math.sqrt(2.0 * S)
-    mu = alpha * math.sqrt(2.0 / S)
+    S = x[3] if is_full(x) else torch.as_tensor(S_SLOPE, dtype=DT)
+    A = D0 / (S - 1.0) * torch.exp(alpha * r0 * torch.sqrt(2.0 * S))
+    B = D0 * S / (S - 1.0) * torch.exp(alpha * r0 * torch.sqrt(2.0 / S))
+    lam = alpha * torch.sqrt(2.0 * S)
+    mu = alpha * torch.sqrt(2.0 / S)
     return A, B, lam, mu
+
+
+def angular(cos: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """g(theta): beta (cos - h)^2 (Sec. II.B, Eq. 10) or Tersoff's g^T (Sec. II.A, Eq. 8)."""
+    if is_full(x):
+        gamma, c, d, h = x[4], x[6], x[7], x[8]
+        return gamma * (1.0 + c * c / (d * d) - c * c / (d * d + (cos - h) ** 2))
+    beta, h = x[3], x[5]
+    return beta * (cos - h) ** 2
+
+
+def bond_order_exponent(x: torch.Tensor) -> torch.Tensor:
+    """n of b = (1 + zeta^n)^(-1/(2n))."""
+    return x[5] if is_full(x) else x[4]
 
 
 def cutoff(r: torch.Tensor, R1: float, R2: float) -> torch.Tensor:
@@ -78,7 +105,7 @@ def site_energies(d: torch.Tensor, center: np.ndarray, p: np.ndarray, q: np.ndar
     """U_i for every atom, given the bond vectors d[e] = r_j + T - r_i of each
     neighbour entry e = (i, j, T) and the ordered entry pairs (p, q) with a common
     centre (Sec. II.A Eqs. 1-9, Sec. II.B Eq. 10)."""
-    beta, n, h = x[3], x[4], x[5]
+    n = bond_order_exponent(x)
     A, B, lam, mu = derived_params(x)
     r = torch.sqrt((d * d).sum(dim=1))
     fc = cutoff(r, R1, R2)
@@ -87,7 +114,7 @@ def site_energies(d: torch.Tensor, center: np.ndarray, p: np.ndarray, q: np.ndar
     pt = torch.as_tensor(p)
     qt = torch.as_tensor(q)
     cos = (d[pt] * d[qt]).sum(dim=1) / (r[pt] * r[qt])
-    g = beta * (cos - h) ** 2
+    g = angular(cos, x)
     zeta = torch.zeros_like(r).index_add(0, pt, fc[qt] * g)
     positive = zeta > 0
     zsafe = torch.where(positive, zeta, torch.ones_like(zeta))
@@ -222,7 +249,7 @@ def fitness_grad(structs, X, refs, weights=(1.0, 1.0, 1.0), R1: float = 2.8, R2:
     top = topology or _Topology(structs, R2)
     X = np.atleast_2d(np.asarray(X, dtype=np.float64))
     Z = np.zeros((X.shape[0], 4))
-    G = np.zeros((X.shape[0], 6))
+    G = np.zeros((X.shape[0], X.shape[1]))
     for c in range(X.shape[0]):
         xt = _as_x(X[c]).clone().requires_grad_(True)
         terms = _fitness_terms(top, xt, refs, weights, R1, R2, True)

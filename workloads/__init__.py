@@ -40,6 +40,10 @@ TABLE2_R2 = 3.2
 # these limits contain Table 2 and keep every parameter of order unity.
 PARAM_LO = (2.0, 1.0, 2.0, 0.1, 0.5, -1.0)
 PARAM_HI = (5.0, 2.0, 2.6, 1.0, 1.5, 0.0)
+# Nine-parameter Tersoff form [D0, alpha, r0, S, gamma, n, c, d, h]: a box of
+# order-unity values around the minimal potential's (S = 2 inside it).
+FULL_LO = (2.0, 1.0, 2.0, 1.5, 0.05, 0.5, 0.5, 0.5, -1.0)
+FULL_HI = (5.0, 2.0, 2.6, 3.0, 1.0, 1.5, 3.0, 3.0, 0.0)
 
 A_SI = 5.43                     # diamond Si lattice constant used for the cells (A)
 RHO_SI = 0.04996                # 2.33 g/cm^3 in atoms / A^3
@@ -123,6 +127,21 @@ def deform(pos: np.ndarray, cell: np.ndarray, F: np.ndarray):
 
 def displace(rng: np.random.Generator, pos: np.ndarray, sigma: float) -> np.ndarray:
     return pos + rng.normal(0.0, sigma, size=pos.shape)
+
+
+def draw_params_full(rng: np.random.Generator, count: int) -> np.ndarray:
+    """Nine-parameter Tersoff sets drawn uniformly inside their box, [count, 9]."""
+    u = rng.uniform(0.0, 1.0, size=(count, 9))
+    lo = np.asarray(FULL_LO)
+    hi = np.asarray(FULL_HI)
+    return lo + u * (hi - lo)
+
+
+def minimal_as_full(x: np.ndarray, d: float, c: float) -> np.ndarray:
+    """The nine-parameter set whose g^T approaches beta (cos - h)^2 as d and
+    c / d^2 grow (Sec. II.B): S = 2, gamma = beta d^4 / c^2."""
+    D0, alpha, r0, beta, n, h = x
+    return np.array([D0, alpha, r0, 2.0, beta * d ** 4 / c ** 2, n, c, d, h])
 
 
 def draw_params(rng: np.random.Generator, count: int) -> np.ndarray:

@@ -14,7 +14,8 @@ parameter set evaluated by the library's float64 path.  The same run also
 measures the plain schedule (one launch per candidate and structure), the
 fitness gradient, uneven batching (500 candidates x 300 structures of 8-512
 atoms), the gradient over those structures (64 candidates), GA generations
-with gradient refinement over them and the 64,000-atom force call, and times
+with gradient refinement over them, the GA batch with nine-parameter
+Tersoff-form candidates and the 64,000-atom force call, and times
 the CPU oracle on a bounded sample.  Prints
 one JSON line on stdout; progress goes to stderr.
 """
@@ -63,6 +64,8 @@ def parse():
                     help="64,000-atom force calls (0: skip)")
     ap.add_argument("--ga-generations", type=int, default=10,
                     help="GA generations with gradient refinement over the uneven set (0: skip)")
+    ap.add_argument("--tf-steps", type=int, default=50,
+                    help="generations of the Tersoff-form (9-parameter) GA batch (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-time budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -235,6 +238,30 @@ def ga_generations(args, api, torch, W, dev):
     return out
 
 
+def tersoff_form_batch(args, api, torch, W, dev):
+    """The GA fitness batch with nine-parameter Tersoff-form candidates
+    (fitness_eval_tf): same structures, population size and launch shape as the
+    headline workload."""
+    wl = W.config2_tersoff_form()
+    s = wl.structs
+    P = wl.population.shape[0]
+    ts, _, _ = make_set(api, torch, wl)
+    X = torch.as_tensor(wl.population, dtype=torch.float64, device=dev).contiguous()
+    Z = torch.empty(P, 4, dtype=torch.float64, device=dev)
+    if not args.no_tune:
+        ts.autotune(P, "fp32", args.tune_cache)          # shape shared with the minimal form
+    t, prof = time_generations(torch, ts, X, Z, args.tf_steps, 5)
+    kernel_ms = prof[0] / max(prof[1], 1)
+    out = {"workload": wl.name, "value": P * s.n_atoms * args.tf_steps / t.seconds,
+           "unit": "atom·candidate evals/s", "ms_per_step": t.seconds / args.tf_steps * 1e3,
+           "steps": args.tf_steps, "population": P, "batched_kernel_ms": kernel_ms,
+           "seeds": wl.seeds}
+    log(f"Tersoff form batched: {out['ms_per_step']:.4f} ms/generation, {out['value']:.4e} "
+        f"atom*cand/s, kernel {kernel_ms:.4f} ms")
+    ts.close()
+    return out
+
+
 def force_call(args, api, torch, W, dev):
     wl = W.config5()
     s = wl.structs
@@ -352,6 +379,8 @@ def main():
         workloads["force_call_64k"] = force_call(args, api, torch, W, dev)
     if args.ga_generations > 0:
         workloads["ga_refined"] = ga_generations(args, api, torch, W, dev)
+    if args.tf_steps > 0:
+        workloads["tersoff_form"] = tersoff_form_batch(args, api, torch, W, dev)
 
     line = {
         "metric": "atom·candidate Tersoff force evals/s and fitness-grad evals/s, batched vs plain",

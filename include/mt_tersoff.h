@@ -36,6 +36,16 @@
  *   not a call error: its outputs are NaN and the other candidates are
  *   unaffected.
  * Threads: an mt_set may be used from one thread at a time.
+ *
+ * Tersoff form: tersoff_eval_tf and fitness_eval_tf take the nine-parameter
+ * form of Sec. II.A (Eqs. 2-9 with Tersoff's angular function, Eq. 8) written
+ * through Eqs. 11-14 with a free slope S:
+ *   x[p*9 + k], k = 0..8 = D0 (eV), alpha (1/A), r0 (A), S, gamma, n, c, d, h;
+ *   A = D0/(S-1) exp(alpha r0 sqrt(2S)), B = S D0/(S-1) exp(alpha r0 sqrt(2/S)),
+ *   lambda = alpha sqrt(2S), mu = alpha sqrt(2/S),
+ *   zeta_ij = sum_k f_C(r_ik) gamma (1 + c^2/d^2 - c^2/(d^2 + (cos theta_ijk - h)^2)).
+ *   Device float64 [P][9].  Outside the domain: non-finite, D0 <= 0, alpha <= 0,
+ *   S <= 1, gamma < 0, n <= 0 or d = 0 (NaN outputs for that candidate).
  */
 #ifndef MT_TERSOFF_H
 #define MT_TERSOFF_H
@@ -156,6 +166,15 @@ int tersoff_eval(mt_set* set, const double* x, int P, int precision, int schedul
                  const double* vel, double* heat_current, void* stream);
 
 /*
+ * tersoff_eval for the nine-parameter Tersoff form (Sec. II.A, Eqs. 2-9, with
+ * Eqs. 11-14 at a free slope S): x is device [P][9] as described at the top
+ * of this file; every other argument, output and error as for tersoff_eval.
+ */
+int tersoff_eval_tf(mt_set* set, const double* x, int P, int precision, int schedule,
+                    double* energy, double* force, double* virial, double* atom_virial,
+                    const double* vel, double* heat_current, void* stream);
+
+/*
  * Fitness of P parameter sets against the attached reference (Sec. III.B):
  *   Z_e = sqrt(sum_s (e_s - e*_s)^2 / sum_s e*_s^2), e_s = E_s / N_s,
  *   Z_v the same over the six virial-per-atom components of every structure,
@@ -166,6 +185,15 @@ int tersoff_eval(mt_set* set, const double* x, int P, int precision, int schedul
  */
 int fitness_eval(mt_set* set, const double* x, int P, const double* w, int precision,
                  int schedule, double* Z, void* stream);
+
+/*
+ * fitness_eval for the nine-parameter Tersoff form (the Sec. III.B fitness of
+ * the Sec. II.A potential): x is device [P][9] as described at the top of this
+ * file; w, Z, schedule, precision and errors as for fitness_eval.  There is no
+ * gradient entry point for this form.
+ */
+int fitness_eval_tf(mt_set* set, const double* x, int P, const double* w, int precision,
+                    int schedule, double* Z, void* stream);
 
 /*
  * Fitness and its gradient dZ/dx with respect to the six parameters (the

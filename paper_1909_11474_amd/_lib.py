@@ -41,7 +41,9 @@ SIGNATURES = {
     "mt_set_stats": (_i, [_vp, ctypes.POINTER(ctypes.c_int64)]),
     "mt_set_neighbors": (_i, [_vp, _vp, _vp, _vp, _vp]),
     "tersoff_eval": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "tersoff_eval_tf": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fitness_eval": (_i, [_vp, _vp, _i, ctypes.POINTER(_d), _i, _i, _vp, _vp]),
+    "fitness_eval_tf": (_i, [_vp, _vp, _i, ctypes.POINTER(_d), _i, _i, _vp, _vp]),
     "fitness_grad": (_i, [_vp, _vp, _i, ctypes.POINTER(_d), _i, _vp, _vp, _vp]),
     "mt_autotune": (_i, [_vp, _i, _i, ctypes.c_char_p]),
     "mt_profile_enable": (_i, [_vp, _i]),

@@ -80,13 +80,15 @@ class TersoffSet:
     def _stream(self):
         return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
 
-    def _x(self, x) -> torch.Tensor:
+    def _x(self, x, widths=(6, 9)) -> torch.Tensor:
+        """[P, 6] minimal-potential or [P, 9] Tersoff-form parameter sets."""
         xt = torch.as_tensor(x) if not torch.is_tensor(x) else x
         xt = xt.detach().to(device=self.device, dtype=torch.float64)
         if xt.dim() == 1:
             xt = xt[None]
-        if xt.dim() != 2 or xt.shape[1] != 6:
-            raise ValueError(f"x must be [P, 6], got {tuple(xt.shape)}")
+        if xt.dim() != 2 or xt.shape[1] not in widths:
+            want = " or ".join(f"[P, {w}]" for w in widths)
+            raise ValueError(f"x must be {want}, got {tuple(xt.shape)}")
         return xt.contiguous()
 
     def close(self):
@@ -141,7 +143,8 @@ class TersoffSet:
     def tersoff_eval(self, x, precision="fp32", schedule="batched", energy=True, forces=True,
                      virial=True, atom_virial=False, velocities=None):
         """Energies [P,S], forces [P,N,3], virials [P,S,6], per-atom virials [P,N,3,3]
-        and heat current [P,3] (when velocities [N,3] in A/fs are given)."""
+        and heat current [P,3] (when velocities [N,3] in A/fs are given).  x is
+        [P, 6] (minimal potential) or [P, 9] (Tersoff form: tersoff_eval_tf)."""
         xt = self._x(x)
         P = xt.shape[0]
         kw = dict(dtype=torch.float64, device=self.device)
@@ -157,10 +160,11 @@ class TersoffSet:
                 v = torch.as_tensor(np.asarray(velocities, dtype=np.float64) if not torch.is_tensor(velocities) else velocities)
                 vel = v.to(torch.float64).t().contiguous().to(self.device)
                 J = torch.empty(P, 3, **kw)
-            rc = self._lib.tersoff_eval(self._handle, _ptr(xt), P, _prec(precision), _sched(schedule),
-                                        _ptr(E), _ptr(F), _ptr(W), _ptr(Wi), _ptr(vel), _ptr(J),
-                                        self._stream())
-        L.check(rc, "tersoff_eval")
+            name = "tersoff_eval_tf" if xt.shape[1] == 9 else "tersoff_eval"
+            rc = getattr(self._lib, name)(self._handle, _ptr(xt), P, _prec(precision),
+                                          _sched(schedule), _ptr(E), _ptr(F), _ptr(W), _ptr(Wi),
+                                          _ptr(vel), _ptr(J), self._stream())
+        L.check(rc, name)
         if E is not None:
             out["E"] = E
         if F is not None:
@@ -175,15 +179,17 @@ class TersoffSet:
 
     def fitness(self, x, weights=(1.0, 1.0, 1.0), precision="fp32", schedule="batched",
                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
-        """[P, 4] = Z, Z_e, Z_v, Z_f (device tensor, float64)."""
+        """[P, 4] = Z, Z_e, Z_v, Z_f (device tensor, float64); x is [P, 6] or, for
+        the Tersoff form (fitness_eval_tf), [P, 9]."""
         xt = self._x(x)
         P = xt.shape[0]
         w = (ctypes.c_double * 3)(*[float(v) for v in weights])
         with torch.cuda.device(self.device):
             Z = out if out is not None else torch.empty(P, 4, dtype=torch.float64, device=self.device)
-            rc = self._lib.fitness_eval(self._handle, _ptr(xt), P, w, _prec(precision),
-                                        _sched(schedule), _ptr(Z), self._stream())
-        L.check(rc, "fitness_eval")
+            name = "fitness_eval_tf" if xt.shape[1] == 9 else "fitness_eval"
+            rc = getattr(self._lib, name)(self._handle, _ptr(xt), P, w, _prec(precision),
+                                          _sched(schedule), _ptr(Z), self._stream())
+        L.check(rc, name)
         return Z
 
     def fitness_call(self, x: torch.Tensor, Z: torch.Tensor, weights=(1.0, 1.0, 1.0),
@@ -193,8 +199,8 @@ class TersoffSet:
         return FitnessCall(self, x, Z, weights, precision, schedule)
 
     def fitness_grad(self, x, weights=(1.0, 1.0, 1.0), precision="fp32"):
-        """(Z [P, 4], dZ/dx [P, 6]) as device tensors."""
-        xt = self._x(x)
+        """(Z [P, 4], dZ/dx [P, 6]) as device tensors (minimal potential only)."""
+        xt = self._x(x, widths=(6,))
         P = xt.shape[0]
         w = (ctypes.c_double * 3)(*[float(v) for v in weights])
         with torch.cuda.device(self.device):
@@ -224,20 +230,22 @@ class TersoffSet:
 
 
 class FitnessCall:
-    """fitness_eval bound to fixed device tensors x [P, 6] and Z [P, 4] (float64,
-    contiguous, on the set's device).  Calling it enqueues one evaluation on the
-    current stream; the contents of x may change between calls."""
+    """fitness_eval bound to fixed device tensors x [P, 6] (fitness_eval_tf for
+    [P, 9]) and Z [P, 4] (float64, contiguous, on the set's device).  Calling it
+    enqueues one evaluation on the current stream; the contents of x may change
+    between calls."""
 
     def __init__(self, tset: TersoffSet, x: torch.Tensor, Z: torch.Tensor, weights, precision, schedule):
         if not (torch.is_tensor(x) and x.dtype == torch.float64 and x.is_contiguous()
-                and x.device == tset.device and x.dim() == 2 and x.shape[1] == 6):
-            raise ValueError("x must be a contiguous float64 [P, 6] tensor on the set's device")
+                and x.device == tset.device and x.dim() == 2 and x.shape[1] in (6, 9)):
+            raise ValueError("x must be a contiguous float64 [P, 6] or [P, 9] tensor on the set's device")
         P = x.shape[0]
         if not (torch.is_tensor(Z) and Z.dtype == torch.float64 and Z.is_contiguous()
                 and Z.device == tset.device and tuple(Z.shape) == (P, 4)):
             raise ValueError("Z must be a contiguous float64 [P, 4] tensor on the set's device")
         self.tset, self.x, self.Z = tset, x, Z
-        self._fn = tset._lib.fitness_eval
+        self._name = "fitness_eval_tf" if x.shape[1] == 9 else "fitness_eval"
+        self._fn = getattr(tset._lib, self._name)
         self._w = (ctypes.c_double * 3)(*[float(v) for v in weights])
         self._args = (tset._handle, ctypes.c_void_p(x.data_ptr()), int(P), self._w,
                       _prec(precision), _sched(schedule), ctypes.c_void_p(Z.data_ptr()))
@@ -246,7 +254,7 @@ class FitnessCall:
         s = stream if stream is not None else torch.cuda.current_stream(self.tset.device)
         rc = self._fn(*self._args, ctypes.c_void_p(s.cuda_stream))
         if rc:
-            L.check(rc, "fitness_eval")
+            L.check(rc, self._name)
         return self.Z
 
 

@@ -207,9 +207,11 @@ int mt_set_neighbors(const mt_set* set, int32_t* i, int32_t* j, int32_t* shift, 
     return export_neighbors(set, i, j, shift, (hipStream_t)stream);
 }
 
-int tersoff_eval(mt_set* set, const double* x, int P, int precision, int schedule, double* energy,
-                 double* force, double* virial, double* atom_virial, const double* vel,
-                 double* heat_current, void* stream) {
+}  // extern "C"
+
+static int eval_impl(mt_set* set, const double* x, int form, int P, int precision, int schedule,
+                     double* energy, double* force, double* virial, double* atom_virial,
+                     const double* vel, double* heat_current, void* stream) {
     TRY(check_common(set, x, P, precision));
     if (schedule != MT_BATCHED && schedule != MT_PLAIN)
         return fail(MT_EINVAL, "schedule must be MT_BATCHED or MT_PLAIN");
@@ -217,6 +219,7 @@ int tersoff_eval(mt_set* set, const double* x, int P, int precision, int schedul
     hipStream_t st = (hipStream_t)stream;
     TRY(ensure_workspace(set, P, kNVEval));
     set->cur_x = x;
+    set->cur_form = form;
     if (schedule == MT_BATCHED) {
         const LaunchCfg cfg = cfg_for(set, P, precision);
         TRY(launch_batched(set, cfg, P, precision, MODE_EVAL, vel, force, atom_virial, st));
@@ -227,9 +230,10 @@ int tersoff_eval(mt_set* set, const double* x, int P, int precision, int schedul
     return launch_finalize_eval(set, P, energy, virial, heat_current, st);
 }
 
-static int fitness_sequence(mt_set* set, const double* x, int P, const double* w, int precision,
-                            int schedule, double* Z, hipStream_t st) {
+static int fitness_sequence(mt_set* set, const double* x, int form, int P, const double* w,
+                            int precision, int schedule, double* Z, hipStream_t st) {
     set->cur_x = x;
+    set->cur_form = form;
     if (schedule == MT_BATCHED) {
         const LaunchCfg cfg = cfg_for(set, P, precision);
         TRY(launch_batched(set, cfg, P, precision, MODE_FIT, nullptr, nullptr, nullptr, st));
@@ -249,8 +253,8 @@ static int check_fitness(mt_set* set, const double* x, int P, const double* w, i
     return MT_OK;
 }
 
-int fitness_eval(mt_set* set, const double* x, int P, const double* w, int precision, int schedule,
-                 double* Z, void* stream) {
+static int fitness_impl(mt_set* set, const double* x, int form, int P, const double* w,
+                        int precision, int schedule, double* Z, void* stream) {
     TRY(check_fitness(set, x, P, w, precision, Z));
     if (schedule != MT_BATCHED && schedule != MT_PLAIN)
         return fail(MT_EINVAL, "schedule must be MT_BATCHED or MT_PLAIN");
@@ -258,25 +262,25 @@ int fitness_eval(mt_set* set, const double* x, int P, const double* w, int preci
     TRY(ensure_workspace(set, P, kNVFit));
     const LaunchCfg cfg = cfg_for(set, P, precision);
     if (schedule == MT_PLAIN || set->profiling || !cfg.graph)
-        return fitness_sequence(set, x, P, w, precision, schedule, Z, st);
+        return fitness_sequence(set, x, form, P, w, precision, schedule, Z, st);
 
     // Batched: replay a captured graph of the batched kernel(s) and finalize.
     GraphKey key;
-    key.x = x; key.Z = Z; key.P = P; key.precision = precision;
+    key.x = x; key.Z = Z; key.P = P; key.precision = precision; key.form = form;
     key.block = cfg.block; key.tile = cfg.tile; key.persistent = cfg.persistent;
     key.w[0] = w[0]; key.w[1] = w[1]; key.w[2] = w[2];
     size_t hit = set->graphs.size();
     for (size_t i = 0; i < set->graphs.size(); ++i)
         if (set->graphs[i].key == key) { hit = i; break; }
     if (hit == set->graphs.size()) {
-        ItemPlan* plan = get_plan(set, P, cfg, precision == MT_FP64 ? FAM_FIT64 : FAM_FIT32);
+        ItemPlan* plan = get_plan(set, P, cfg, family_for(precision, MODE_FIT, form));
         if (!plan) return fail(MT_EINVAL, "could not build the work list");
         TRY(reserve_twopass(set, plan, P, precision));     // allocate before capture
         if (!set->capture_stream) HIPCHECK(hipStreamCreateWithFlags(&set->capture_stream, hipStreamNonBlocking));
         GraphEntry ge;
         ge.key = key;
         HIPCHECK(hipStreamBeginCapture(set->capture_stream, hipStreamCaptureModeThreadLocal));
-        int rc = fitness_sequence(set, x, P, w, precision, schedule, Z, set->capture_stream);
+        int rc = fitness_sequence(set, x, form, P, w, precision, schedule, Z, set->capture_stream);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(set->capture_stream, &graph);
         if (rc != MT_OK) {
@@ -306,6 +310,32 @@ int fitness_eval(mt_set* set, const double* x, int P, const double* w, int preci
     return MT_OK;
 }
 
+extern "C" {
+
+int tersoff_eval(mt_set* set, const double* x, int P, int precision, int schedule, double* energy,
+                 double* force, double* virial, double* atom_virial, const double* vel,
+                 double* heat_current, void* stream) {
+    return eval_impl(set, x, 0, P, precision, schedule, energy, force, virial, atom_virial, vel,
+                     heat_current, stream);
+}
+
+int tersoff_eval_tf(mt_set* set, const double* x, int P, int precision, int schedule,
+                    double* energy, double* force, double* virial, double* atom_virial,
+                    const double* vel, double* heat_current, void* stream) {
+    return eval_impl(set, x, 1, P, precision, schedule, energy, force, virial, atom_virial, vel,
+                     heat_current, stream);
+}
+
+int fitness_eval(mt_set* set, const double* x, int P, const double* w, int precision, int schedule,
+                 double* Z, void* stream) {
+    return fitness_impl(set, x, 0, P, w, precision, schedule, Z, stream);
+}
+
+int fitness_eval_tf(mt_set* set, const double* x, int P, const double* w, int precision,
+                    int schedule, double* Z, void* stream) {
+    return fitness_impl(set, x, 1, P, w, precision, schedule, Z, stream);
+}
+
 int fitness_grad(mt_set* set, const double* x, int P, const double* w, int precision, double* Z,
                  double* dZdx, void* stream) {
     TRY(check_fitness(set, x, P, w, precision, Z));
@@ -318,7 +348,7 @@ int fitness_grad(mt_set* set, const double* x, int P, const double* w, int preci
                                    std::to_string(MT_MAX_GRAD_NBR));
     hipStream_t st = (hipStream_t)stream;
     TRY(ensure_workspace(set, P, kNVFit));
-    TRY(fitness_sequence(set, x, P, w, precision, MT_BATCHED, Z, st));
+    TRY(fitness_sequence(set, x, 0, P, w, precision, MT_BATCHED, Z, st));
     const LaunchCfg cfg = cfg_for(set, P, precision);
     TRY(launch_adjoint(set, cfg, P, precision, w, Z, st));
     return launch_finalize_grad(set, P, Z, dZdx, st);
@@ -408,6 +438,7 @@ int mt_autotune(mt_set* set, int P, int precision, const char* cache_path) {
     int rc = ensure_workspace(set, P, kNVFit);
     if (rc) { (void)hipStreamDestroy(st); return rc; }
     set->cur_x = xb.as<double>();
+    set->cur_form = 0;
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
@@ -430,7 +461,7 @@ int mt_autotune(mt_set* set, int P, int precision, const char* cache_path) {
         // one generation: batched kernel(s) and the finalize kernel
         auto gen = [&]() -> int {
             if (have_ref)
-                return fitness_sequence(set, xb.as<double>(), P, wt, precision, MT_BATCHED, zb.as<double>(), st);
+                return fitness_sequence(set, xb.as<double>(), 0, P, wt, precision, MT_BATCHED, zb.as<double>(), st);
             return launch_batched(set, c, P, precision, MODE_FIT, nullptr, nullptr, nullptr, st);
         };
         if (gen() != MT_OK) continue;

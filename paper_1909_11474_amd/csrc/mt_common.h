@@ -40,28 +40,43 @@ constexpr int kMaxBatched = 512;   // largest structure of the batched kernel
 constexpr int kNVFit = 8;          // partial sums per slot: E, W6, |F - F*|^2
 constexpr int kNVEval = 16;        // E, W6, |F-F*|^2, J3, unused
 constexpr int kNVGrad = 8;         // dZ/dx (6), unused (2)
-constexpr int kNParam = 20;        // per-candidate decoded parameter record
+constexpr int kNParam = 24;        // per-candidate decoded parameter record
 
 // Decoded parameter record (float or double), filled per work item in LDS.
+// Both potential forms share it: f_R = DR e^{-lambda (r - r0)},
+// f_A = DA e^{-mu (r - r0)} with lambda = alpha sqrt(2S), mu = alpha sqrt(2/S),
+// DR = D0/(S-1), DA = S D0/(S-1) (Sec. II.B Eqs. 11-14; S = 2 in the minimal
+// potential); zeta = ZS sum_k f_C g(theta) with g = (cos - h)^2 and ZS = beta
+// (minimal), or g = g^T = gamma + K t^2 / (d^2 + t^2), t = cos - h,
+// K = gamma c^2 / d^2 and ZS = 1 (Tersoff form, Sec. II.A Eq. 8).
 enum ParamIndex {
-    P_AL = 0,       // alpha * log2(e)
+    P_AA = 0,       // mu log2(e)
     P_R0HI = 1,     // r0 (float: high part)
     P_R0LO = 2,     // r0 - r0_hi (float only)
-    P_D0 = 3,
-    P_2D0 = 4,
-    P_BETA = 6,
+    P_DR = 3,
+    P_DA = 4,
+    P_AR = 5,       // lambda log2(e)
+    P_ZS = 6,       // zeta scale: beta, or 1
     P_N = 7,
     P_NINV2N = 8,   // -1 / (2 n)
     P_H = 9,
     P_VALID = 10,   // 1 if the candidate is inside the potential's domain
-    P_HALPHA = 11,  // alpha / 2
-    P_HBETA = 12,   // beta / 2
+    P_HMU = 11,     // mu / 2
+    P_CCS = 12,     // gradient coefficient scale: beta / 2, or 1 / 2
     // float records: low parts (value - float(value)) of the parameters the
     // float64 energy terms use; zero in double records
-    P_ALLO = 13,
-    P_D0LO = 14,
+    P_AALO = 13,
+    P_DRLO = 14,
     P_NLO = 15,
-    P_NINV2NLO = 16
+    P_NINV2NLO = 16,
+    P_ARLO = 17,
+    P_DALO = 18,
+    P_HLAMBDA = 19, // lambda / 2
+    // Tersoff angular function
+    P_GAM = 20,     // gamma
+    P_K = 21,       // gamma c^2 / d^2
+    P_D2 = 22,      // d^2
+    P_KD2 = 23      // K d^2
 };
 
 struct Item {       // one (structure, candidate range) work item of the batched kernel

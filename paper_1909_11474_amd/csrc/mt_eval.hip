@@ -30,8 +30,8 @@ namespace mt {
 // ---------------------------------------------------------------------------
 // Finalize kernels (one block per candidate, fixed summation order).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool cand_valid(const double* x, int c) {
-    return params_valid(x + 6 * (size_t)c);
+__device__ __forceinline__ bool cand_valid(const double* x, int c, int full) {
+    return full ? params_valid<true>(x + 9 * (size_t)c) : params_valid<false>(x + 6 * (size_t)c);
 }
 
 __device__ __forceinline__ void block_sum3(double* a, double (*sh)[256]) {
@@ -51,7 +51,8 @@ struct FinArgs {
     int nv;
     const double* eref; const double* wref;
     double Qe, Qv, Qf, we, wv, wf;
-    const double* x;           // [P][6]
+    const double* x;           // [P][6] (minimal) or [P][9] (Tersoff form)
+    int full;                  // 1: x holds Tersoff-form parameter sets
     double* Z;                 // [P][4]
     double* coef;              // [P][S][8] or null (gradient coefficients)
     double* energy; double* virial; double* heat;
@@ -145,7 +146,7 @@ __global__ __launch_bounds__(256) void k_finalize_fit(FinArgs F) {
     }
     block_sum3(acc, sh);
     if (threadIdx.x == 0) {
-        const bool ok = cand_valid(F.x, c);
+        const bool ok = cand_valid(F.x, c, F.full);
         const double Ze = sqrt(acc[0] / F.Qe), Zv = sqrt(acc[1] / F.Qv), Zf = sqrt(acc[2] / F.Qf);
         const double Z = F.we * Ze + F.wv * Zv + F.wf * Zf;
         const double nan = __longlong_as_double(0x7ff8000000000000ll);
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(256) void k_finalize_fit_wave(FinArgs F, int P) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) acc[k] += __shfl_xor(acc[k], o, 64);
     if (lane == 0) {
-        const bool ok = cand_valid(F.x, c);
+        const bool ok = cand_valid(F.x, c, F.full);
         const double Ze = sqrt(acc[0] / F.Qe), Zv = sqrt(acc[1] / F.Qv), Zf = sqrt(acc[2] / F.Qf);
         const double Z = F.we * Ze + F.wv * Zv + F.wf * Zf;
         const double nan = __longlong_as_double(0x7ff8000000000000ll);
@@ -233,7 +234,7 @@ __global__ __launch_bounds__(256) void k_finalize_grad(FinArgs F, double* dZdx) 
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const bool ok = cand_valid(F.x, c);
+        const bool ok = cand_valid(F.x, c, F.full);
         const double nan = __longlong_as_double(0x7ff8000000000000ll);
         for (int k = 0; k < 6; ++k) dZdx[6 * c + k] = ok ? sh[k][0] : nan;
     }
@@ -243,7 +244,7 @@ __global__ __launch_bounds__(256) void k_finalize_eval(FinArgs F) {
     __shared__ double sh[11][256];
     const int c = blockIdx.x;
     const SetDev& d = F.set;
-    const bool ok = cand_valid(F.x, c);
+    const bool ok = cand_valid(F.x, c, F.full);
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
     double jacc[3] = {0, 0, 0};
     for (int s = 0; F.coop && s < d.S; ++s) {
@@ -298,13 +299,24 @@ FinArgs make_fin(mt_set* set, int nv, const double* partial) {
     F.wref = set->wref.as<double>();
     F.Qe = set->Q[0]; F.Qv = set->Q[1]; F.Qf = set->Q[2];
     F.x = set->cur_x;
+    F.full = set->cur_form;
     F.coop = 0;
     for (int s = 0; s < set->S; ++s)
         if (set->h_slot[s + 1] - set->h_slot[s] > kCoopSlots) F.coop = 1;
     return F;
 }
 
-int family_elem(int fam) { return (fam == FAM_FIT64 || fam == FAM_EVAL64 || fam == FAM_ADJ64) ? 8 : 4; }
+bool family_f64(int fam) {
+    return fam == FAM_FIT64 || fam == FAM_EVAL64 || fam == FAM_ADJ64 || fam == FAM_FIT64F ||
+           fam == FAM_EVAL64F;
+}
+bool family_fit(int fam) {
+    return fam == FAM_FIT32 || fam == FAM_FIT64 || fam == FAM_FIT32F || fam == FAM_FIT64F;
+}
+bool family_full(int fam) {
+    return fam == FAM_FIT32F || fam == FAM_EVAL32F || fam == FAM_FIT64F || fam == FAM_EVAL64F;
+}
+int family_elem(int fam) { return family_f64(fam) ? 8 : 4; }
 bool family_adjoint(int fam) { return fam == FAM_ADJ32 || fam == FAM_ADJ64; }
 
 // LDS of one item: parameter records, bond-gradient exchange slots (4 values
@@ -329,16 +341,25 @@ hipError_t launch_family(int fam, int mc, dim3 g, dim3 b, size_t lds, hipStream_
         case FAM_EVAL64: return launch_eval64(mc, g, b, lds, st, Ad, e0, e1);
         case FAM_ADJ32: return launch_adj32(mc, g, b, lds, st, Af, e0, e1);
         case FAM_ADJ64: return launch_adj64(mc, g, b, lds, st, Ad, e0, e1);
+        case FAM_FIT32F: return launch_fit32f(mc, g, b, lds, st, Af, e0, e1);
+        case FAM_EVAL32F: return launch_eval32f(mc, g, b, lds, st, Af, e0, e1);
+        case FAM_FIT64F: return launch_fit64f(mc, g, b, lds, st, Ad, e0, e1);
+        case FAM_EVAL64F: return launch_eval64f(mc, g, b, lds, st, Ad, e0, e1);
     }
     return hipErrorInvalidValue;
 }
 
-int family_for(int precision, int mode) {
-    if (mode == MODE_FIT) return precision == MT_FP64 ? FAM_FIT64 : FAM_FIT32;
-    return precision == MT_FP64 ? FAM_EVAL64 : FAM_EVAL32;
-}
-
 }  // namespace
+
+int family_for(int precision, int mode, int form) {
+    const bool f64 = precision == MT_FP64;
+    if (form) {
+        if (mode == MODE_FIT) return f64 ? FAM_FIT64F : FAM_FIT32F;
+        return f64 ? FAM_EVAL64F : FAM_EVAL32F;
+    }
+    if (mode == MODE_FIT) return f64 ? FAM_FIT64 : FAM_FIT32;
+    return f64 ? FAM_EVAL64 : FAM_EVAL32;
+}
 
 const std::vector<int>& family_classes(int fam) {
     static const std::vector<int> k[NFAM] = {
@@ -348,6 +369,10 @@ const std::vector<int>& family_classes(int fam) {
         {4, 16},             // EVAL64
         {4, 8, 12},          // ADJ32
         {4, 12},             // ADJ64
+        {4, 16},             // FIT32F
+        {4, 16},             // EVAL32F
+        {4, 16},             // FIT64F
+        {4, 16},             // EVAL64F
     };
     return k[fam];
 }
@@ -527,15 +552,16 @@ static int run_plan(mt_set* set, ItemPlan* plan, const LaunchCfg& cfg, int fam, 
             HIPCHECK(launch_family(fam, cp.mc, dim3(cp.n_bins), dim3(cp.block), cp.lds, st, Af, Ad,
                                    prof.e0, prof.e1));
         } else {
-            const bool f64 = fam == FAM_FIT64 || fam == FAM_EVAL64;
-            const int mode = (fam == FAM_FIT32 || fam == FAM_FIT64) ? MODE_FIT : MODE_EVAL;
+            const bool f64 = family_f64(fam);
+            const bool full = family_full(fam);
+            const int mode = family_fit(fam) ? MODE_FIT : MODE_EVAL;
             for (int k = 0; k < cp.n_items; ++k) {
                 const int s = cp.h_items[k].s;
                 const dim3 block(cp.block);
                 const size_t lds = item_lds(set, s, block.x, fam, 1);
                 Af.items = Ad.items = cp.items.as<Item>() + k;
-                HIPCHECK(f64 ? launch_plain64(mode, cp.mc, block, lds, st, Ad)
-                             : launch_plain32(mode, cp.mc, block, lds, st, Af));
+                HIPCHECK(f64 ? launch_plain64(mode, full, cp.mc, block, lds, st, Ad)
+                             : launch_plain32(mode, full, cp.mc, block, lds, st, Af));
             }
         }
     }
@@ -548,7 +574,7 @@ static int launch_twopass(mt_set* set, const std::vector<int>& structs, int P, i
 
 int launch_batched(mt_set* set, const LaunchCfg& cfg, int P, int precision, int mode,
                    const double* vel, double* force, double* atom_virial, hipStream_t st) {
-    const int fam = family_for(precision, mode);
+    const int fam = family_for(precision, mode, set->cur_form);
     ItemPlan* plan = get_plan(set, P, cfg, fam);
     if (!plan) {
         set_error("could not build the work list (block smaller than a structure?)");
@@ -619,9 +645,9 @@ static int launch_twopass_t(mt_set* set, const std::vector<int>& structs, int P,
             dim3 grid(grid_of(ns, 256), nc);
             hipError_t e;
             if constexpr (std::is_same<S, double>::value)
-                e = launch_large64(mc, mode, grid, dim3(256), st, A, L);
+                e = launch_large64(mc, mode, set->cur_form, grid, dim3(256), st, A, L);
             else
-                e = launch_large32(mc, mode, grid, dim3(256), st, A, L);
+                e = launch_large32(mc, mode, set->cur_form, grid, dim3(256), st, A, L);
             HIPCHECK(e);
         }
     }
@@ -684,6 +710,10 @@ static int launch_grad_coef(mt_set* set, int P, const double* w, const double* Z
 
 static int adjoint_common(mt_set* set, const LaunchCfg& cfg, int P, int precision, const double* w,
                           const double* Z, hipStream_t st) {
+    if (set->cur_form != 0) {
+        set_error("the fitness gradient covers the minimal potential only");
+        return MT_EINVAL;
+    }
     TRY_RC(launch_grad_coef(set, P, w, Z, st));
     HIPCHECK(set->partial2.reserve(sizeof(double) * kNVGrad * (size_t)P * set->nslots));
     const int fam = precision == MT_FP64 ? FAM_ADJ64 : FAM_ADJ32;

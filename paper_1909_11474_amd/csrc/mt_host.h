@@ -63,16 +63,22 @@ struct ItemPlan {             // uploaded work lists for one (P, launch shape, k
     std::vector<int> twopass;
 };
 
-// Kernel families: precision x (fitness, energy/force/virial, adjoint).
-enum Family { FAM_FIT32 = 0, FAM_EVAL32, FAM_FIT64, FAM_EVAL64, FAM_ADJ32, FAM_ADJ64, NFAM };
+// Kernel families: precision x (fitness, energy/force/virial, adjoint) for the
+// minimal potential, and precision x (fitness, energy/force/virial) for the
+// nine-parameter Tersoff form (suffix F).
+enum Family {
+    FAM_FIT32 = 0, FAM_EVAL32, FAM_FIT64, FAM_EVAL64, FAM_ADJ32, FAM_ADJ64,
+    FAM_FIT32F, FAM_EVAL32F, FAM_FIT64F, FAM_EVAL64F, NFAM
+};
 
 struct GraphKey {             // what a captured fitness graph depends on
     const void* x = nullptr;
     void* Z = nullptr;
-    int P = 0, precision = 0, block = 0, tile = 0, persistent = 0;
+    int P = 0, precision = 0, block = 0, tile = 0, persistent = 0, form = 0;
     double w[3] = {0, 0, 0};
     bool operator==(const GraphKey& o) const {
-        return x == o.x && Z == o.Z && P == o.P && precision == o.precision && block == o.block &&
+        return x == o.x && Z == o.Z && P == o.P && precision == o.precision && form == o.form &&
+               block == o.block &&
                tile == o.tile && persistent == o.persistent && w[0] == o.w[0] && w[1] == o.w[1] &&
                w[2] == o.w[2];
     }
@@ -112,8 +118,10 @@ struct mt_set {
     mt::DevBuf eref, wref, fref32, fref64;
     double Q[3] = {0, 0, 0};
 
-    // parameter sets of the call being enqueued (device [P][6])
+    // parameter sets of the call being enqueued (device [P][6], or [P][9] for
+    // the Tersoff form) and their form (0 minimal, 1 Tersoff form)
     const double* cur_x = nullptr;
+    int cur_form = 0;
 
     // workspaces
     mt::DevBuf partial;                      // [P][nslots][NV] double
@@ -167,6 +175,8 @@ int launch_finalize_grad(mt_set* set, int P, const double* Z, double* dZdx, hipS
 enum Mode { MODE_FIT = 0, MODE_EVAL = 1 };
 
 ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int family);
+// Batched kernel family of a call: precision x mode x parameter form.
+int family_for(int precision, int mode, int form);
 LaunchCfg default_cfg(const mt_set* set, int P, int precision);
 int class_of(int family, int kmax);
 const std::vector<int>& family_classes(int family);

@@ -4,7 +4,9 @@
 
 namespace mt {
 
-hipError_t launch_plain32(int mode, int mc, dim3 b, size_t lds, hipStream_t st, const BArgs<float>& A) {
+hipError_t launch_plain32(int mode, bool full, int mc, dim3 b, size_t lds, hipStream_t st,
+                          const BArgs<float>& A) {
+    if (full) return launch_plain32f(mode, mc, b, lds, st, A);
     const dim3 g(1);
     if (mode == MODE_FIT) {
         switch (mc) {

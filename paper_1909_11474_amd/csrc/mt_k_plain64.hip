@@ -4,7 +4,9 @@
 
 namespace mt {
 
-hipError_t launch_plain64(int mode, int mc, dim3 b, size_t lds, hipStream_t st, const BArgs<double>& A) {
+hipError_t launch_plain64(int mode, bool full, int mc, dim3 b, size_t lds, hipStream_t st,
+                          const BArgs<double>& A) {
+    if (full) return launch_plain64f(mode, mc, b, lds, st, A);
     const dim3 g(1);
     if (mode == MODE_FIT) {
         switch (mc) {

@@ -42,35 +42,88 @@ namespace mt {
 // is replaced by a harmless stand-in so the arithmetic stays finite; its
 // outputs are set to NaN by the finalize kernels.
 // ---------------------------------------------------------------------------
+// Parameter vectors: minimal [D0, alpha, r0, beta, n, h]; Tersoff form
+// [D0, alpha, r0, S, gamma, n, c, d, h].
+template <bool Full>
+struct Form {
+    static constexpr int nx = Full ? 9 : 6;
+};
+
+template <bool Full>
 __device__ __forceinline__ bool params_valid(const double* __restrict__ x) {
-    const double D0 = x[0], al = x[1], r0 = x[2], be = x[3], n = x[4], h = x[5];
-    return isfinite(D0) && isfinite(al) && isfinite(r0) && isfinite(be) && isfinite(n) &&
-           isfinite(h) && D0 > 0.0 && al > 0.0 && n > 0.0 && be >= 0.0;
+    bool fin = true;
+#pragma unroll
+    for (int k = 0; k < Form<Full>::nx; ++k) fin = fin && isfinite(x[k]);
+    if constexpr (Full) {
+        return fin && x[0] > 0.0 && x[1] > 0.0 && x[3] > 1.0 && x[4] >= 0.0 && x[5] > 0.0 &&
+               x[7] != 0.0;
+    } else {
+        return fin && x[0] > 0.0 && x[1] > 0.0 && x[4] > 0.0 && x[3] >= 0.0;
+    }
 }
 
 template <typename S>
+__device__ __forceinline__ void put_split(S* __restrict__ o, int hi, int lo, double v) {
+    const S h = (S)v;
+    o[hi] = h;
+    o[lo] = (S)(v - (double)h);
+}
+
+// x -> the record of the form-independent site routine (see ParamIndex).
+template <typename S, bool Full>
 __device__ __forceinline__ void decode_record(const double* __restrict__ x, S* __restrict__ o) {
-    double D0 = x[0], al = x[1], r0 = x[2], be = x[3], n = x[4], h = x[5];
-    const bool ok = params_valid(x);
-    if (!ok) { D0 = 3.0; al = 1.4; r0 = 2.2; be = 0.3; n = 0.6; h = -0.6; }
-    o[P_AL] = (S)(al * 1.4426950408889634);
-    const S r0hi = (S)r0;
-    o[P_R0HI] = r0hi;
-    o[P_R0LO] = (S)(r0 - (double)r0hi);
-    o[P_D0] = (S)D0;
-    o[P_2D0] = (S)(2.0 * D0);
-    o[P_BETA] = (S)be;
-    o[P_N] = (S)n;
-    o[P_NINV2N] = (S)(-1.0 / (2.0 * n));
-    o[P_H] = (S)h;
-    o[P_VALID] = ok ? S(1) : S(0);
-    o[P_HALPHA] = (S)(0.5 * al);
-    o[P_HBETA] = (S)(0.5 * be);
-    const double aL = al * 1.4426950408889634, ni = -1.0 / (2.0 * n);
-    o[P_ALLO] = (S)(aL - (double)(S)aL);
-    o[P_D0LO] = (S)(D0 - (double)(S)D0);
-    o[P_NLO] = (S)(n - (double)(S)n);
-    o[P_NINV2NLO] = (S)(ni - (double)(S)ni);
+    const double log2e = 1.4426950408889634;
+    const bool ok = params_valid<Full>(x);
+    if constexpr (Full) {
+        double D0 = x[0], al = x[1], r0 = x[2], Sl = x[3], gam = x[4], n = x[5], c = x[6],
+               d = x[7], h = x[8];
+        if (!ok) { D0 = 3.0; al = 1.4; r0 = 2.2; Sl = 2.0; gam = 0.3; n = 0.6; c = 1.0; d = 1.0; h = -0.6; }
+        const double mu = al * sqrt(2.0 / Sl), lam = al * sqrt(2.0 * Sl);
+        put_split(o, P_AA, P_AALO, mu * log2e);
+        put_split(o, P_AR, P_ARLO, lam * log2e);
+        put_split(o, P_R0HI, P_R0LO, r0);
+        put_split(o, P_DR, P_DRLO, D0 / (Sl - 1.0));
+        put_split(o, P_DA, P_DALO, Sl * D0 / (Sl - 1.0));
+        put_split(o, P_N, P_NLO, n);
+        put_split(o, P_NINV2N, P_NINV2NLO, -1.0 / (2.0 * n));
+        o[P_H] = (S)h;
+        o[P_VALID] = ok ? S(1) : S(0);
+        o[P_HMU] = (S)(0.5 * mu);
+        o[P_HLAMBDA] = (S)(0.5 * lam);
+        o[P_ZS] = S(1);
+        o[P_CCS] = S(0.5);
+        const double K = gam * c * c / (d * d);
+        o[P_GAM] = (S)gam;
+        o[P_K] = (S)K;
+        o[P_D2] = (S)(d * d);
+        o[P_KD2] = (S)(K * d * d);
+    } else {
+        // S = 2: mu = alpha, lambda = 2 alpha, DR = D0, DA = 2 D0.  The slots
+        // that only the Tersoff form reads (P_AR, P_ARLO, P_DALO, P_HLAMBDA,
+        // P_GAM .. P_KD2) are left unwritten: writing them changes the
+        // register allocation of the float fitness kernel's candidate loop
+        // (three more spilled values there, 4 % slower).
+        double D0 = x[0], al = x[1], r0 = x[2], be = x[3], n = x[4], h = x[5];
+        if (!ok) { D0 = 3.0; al = 1.4; r0 = 2.2; be = 0.3; n = 0.6; h = -0.6; }
+        o[P_AA] = (S)(al * log2e);
+        const S r0hi = (S)r0;
+        o[P_R0HI] = r0hi;
+        o[P_R0LO] = (S)(r0 - (double)r0hi);
+        o[P_DR] = (S)D0;
+        o[P_DA] = (S)(2.0 * D0);
+        o[P_ZS] = (S)be;
+        o[P_N] = (S)n;
+        o[P_NINV2N] = (S)(-1.0 / (2.0 * n));
+        o[P_H] = (S)h;
+        o[P_VALID] = ok ? S(1) : S(0);
+        o[P_HMU] = (S)(0.5 * al);
+        o[P_CCS] = (S)(0.5 * be);
+        const double aA = al * log2e, ni = -1.0 / (2.0 * n);
+        o[P_AALO] = (S)(aA - (double)(S)aA);
+        o[P_DRLO] = (S)(D0 - (double)(S)D0);
+        o[P_NLO] = (S)(n - (double)(S)n);
+        o[P_NINV2NLO] = (S)(ni - (double)(S)ni);
+    }
 }
 
 template <typename S>
@@ -83,7 +136,7 @@ struct BArgs {
     SetDev set;
     const Item* items;
     const int* bin_off;
-    const double* x;          // [P][6] parameter sets
+    const double* x;          // [P][6] (minimal) or [P][9] (Tersoff form) parameter sets
     double* partial;          // [P][nslots][nv]
     int nv;
     int ptile;                // largest candidate count of an item in this launch
@@ -181,7 +234,7 @@ __device__ __forceinline__ size_t lds_param_bytes(int ptile) {
     return ((size_t)ptile * kNParam * sizeof(S) + 31) & ~(size_t)31;
 }
 
-template <typename S, int MODE, int M, int GF = 0>
+template <typename S, int MODE, int M, int GF = 0, bool Full = false>
 __device__ __forceinline__ void run_batched(const BArgs<S>& A, const Item& it, const ItemCtx& x,
                                             unsigned char* __restrict__ lds) {
     const SetDev& d = A.set;
@@ -212,7 +265,7 @@ __device__ __forceinline__ void run_batched(const BArgs<S>& A, const Item& it, c
         const bool cok = x.active && group_ok;
         const int clv = group_ok ? cl : 0;
         const int c = it.c0 + clv;
-        Cand<S, S> p;
+        Cand<S, S, Full> p;
         load_cand(pbuf + kNParam * clv, p);
         double U;
         S Gx[MM], Gy[MM], Gz[MM];
@@ -313,17 +366,17 @@ struct ClassLo {
 };
 
 // Decode the item's parameter sets into the LDS records (all threads take part).
-template <typename S>
+template <typename S, bool Full = false>
 __device__ __forceinline__ void decode_item(const BArgs<S>& A, const Item& it, unsigned char* lds) {
     S* pbuf = reinterpret_cast<S*>(lds);
     for (int t = threadIdx.x; t < it.nc; t += blockDim.x)
-        decode_record<S>(A.x + 6 * (size_t)(it.c0 + t), pbuf + kNParam * t);
+        decode_record<S, Full>(A.x + Form<Full>::nx * (size_t)(it.c0 + t), pbuf + kNParam * t);
     __syncthreads();
 }
 
-template <typename S, int MODE, int MC>
+template <typename S, int MODE, int MC, bool Full>
 __device__ __forceinline__ void batched_item(const BArgs<S>& A, const Item& it, unsigned char* lds) {
-    decode_item<S>(A, it, lds);
+    decode_item<S, Full>(A, it, lds);
     const ItemCtx x = item_ctx(A.set, it);
     const int Mi = x.active ? A.set.nnb[x.atom] : -1;
     const int Mw = wave_max_int(Mi);
@@ -339,11 +392,11 @@ __device__ __forceinline__ void batched_item(const BArgs<S>& A, const Item& it, 
         // no branches and no copies around the in-place lane swaps
         if constexpr (MODE == MODE_FIT && sizeof(S) == 4) {
             if (x.g == 64) {
-                run_batched<S, MODE, decltype(mv)::value, 64>(A, it, x, lds);
+                run_batched<S, MODE, decltype(mv)::value, 64, Full>(A, it, x, lds);
                 return;
             }
         }
-        run_batched<S, MODE, decltype(mv)::value>(A, it, x, lds);
+        run_batched<S, MODE, decltype(mv)::value, 0, Full>(A, it, x, lds);
     });
 }
 
@@ -354,14 +407,14 @@ struct WavesPerEU {
     static constexpr int value = (MC <= 4 && sizeof(S) == 4 && MODE == MODE_FIT) ? 4 : 1;
 };
 
-template <typename S, int MODE, int MC>
+template <typename S, int MODE, int MC, bool Full = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S, MODE, MC>::value)))
 void k_batched(BArgs<S> A) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int b0 = A.bin_off[blockIdx.x], b1 = A.bin_off[blockIdx.x + 1];
     for (int i = b0; i < b1; ++i) {
         const Item it = A.items[i];
-        batched_item<S, MODE, MC>(A, it, lds_raw);
+        batched_item<S, MODE, MC, Full>(A, it, lds_raw);
         __syncthreads();
     }
 }
@@ -369,11 +422,11 @@ void k_batched(BArgs<S> A) {
 // The plain schedule: one launch per (candidate, structure), a single block
 // that evaluates the item A.items[0].  The same device code as k_batched,
 // under a kernel name of its own so that profiles keep the two apart.
-template <typename S, int MODE, int MC>
+template <typename S, int MODE, int MC, bool Full = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S, MODE, MC>::value)))
 void k_plain(BArgs<S> A) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
-    batched_item<S, MODE, MC>(A, A.items[0], lds_raw);
+    batched_item<S, MODE, MC, Full>(A, A.items[0], lds_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -532,7 +585,7 @@ struct LArgs {
     void* gbuf;                // [chunk][3][nbs] of S
 };
 
-template <typename S, int M, bool E64>
+template <typename S, int M, bool E64, bool Full>
 __device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L, int la, int atom,
                                                bool active) {
     const SetDev& d = A.set;
@@ -545,8 +598,8 @@ __device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L
     const int Mi = active ? d.nnb[atom] : 0;
     const int lb = active ? d.lbo[atom] : 0;
     S rec[kNParam];
-    decode_record<S>(A.x + 6 * (size_t)c, rec);
-    Cand<S, S> p;
+    decode_record<S, Full>(A.x + Form<Full>::nx * (size_t)c, rec);
+    Cand<S, S, Full> p;
     load_cand(rec, p);
     double U;
     S Gx[MM], Gy[MM], Gz[MM];
@@ -585,7 +638,7 @@ __device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L
 }
 
 // E64: float64 energy terms (the float path's energy/force/virial mode).
-template <typename S, int MC, bool E64>
+template <typename S, int MC, bool E64, bool Full = false>
 __global__ __launch_bounds__(256) void k_large_site(BArgs<S> A, LArgs L) {
     const SetDev& d = A.set;
     const int a0 = d.st_off[L.s], Ns = d.st_off[L.s + 1] - a0;
@@ -596,7 +649,7 @@ __global__ __launch_bounds__(256) void k_large_site(BArgs<S> A, LArgs L) {
     const int Mw = wave_max_int(Mi);
     if (Mw < 0) return;
     dispatch_m<ClassLo<MC>::value, MC>(Mw, [&](auto mv) {
-        run_large_site<S, decltype(mv)::value, E64>(A, L, la, atom, active);
+        run_large_site<S, decltype(mv)::value, E64, Full>(A, L, la, atom, active);
     });
 }
 
@@ -682,12 +735,26 @@ hipError_t launch_adj32(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, cons
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_adj64(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<double>& A,
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-// Plain-schedule launchers (one block, one item); mode is MODE_FIT or MODE_EVAL.
-hipError_t launch_plain32(int mode, int mc, dim3 b, size_t lds, hipStream_t st, const BArgs<float>& A);
-hipError_t launch_plain64(int mode, int mc, dim3 b, size_t lds, hipStream_t st, const BArgs<double>& A);
-hipError_t launch_large32(int mc, int mode, dim3 g, dim3 b, hipStream_t st, const BArgs<float>& A,
-                          const LArgs& L);
-hipError_t launch_large64(int mc, int mode, dim3 g, dim3 b, hipStream_t st, const BArgs<double>& A,
-                          const LArgs& L);
+// Tersoff-form (nine-parameter) batched families.
+hipError_t launch_fit32f(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<float>& A,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_eval32f(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<float>& A,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_fit64f(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<double>& A,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_eval64f(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<double>& A,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// Plain-schedule launchers (one block, one item); mode is MODE_FIT or MODE_EVAL,
+// full selects the Tersoff form.
+hipError_t launch_plain32(int mode, bool full, int mc, dim3 b, size_t lds, hipStream_t st,
+                          const BArgs<float>& A);
+hipError_t launch_plain64(int mode, bool full, int mc, dim3 b, size_t lds, hipStream_t st,
+                          const BArgs<double>& A);
+hipError_t launch_plain32f(int mode, int mc, dim3 b, size_t lds, hipStream_t st, const BArgs<float>& A);
+hipError_t launch_plain64f(int mode, int mc, dim3 b, size_t lds, hipStream_t st, const BArgs<double>& A);
+hipError_t launch_large32(int mc, int mode, int full, dim3 g, dim3 b, hipStream_t st,
+                          const BArgs<float>& A, const LArgs& L);
+hipError_t launch_large64(int mc, int mode, int full, dim3 g, dim3 b, hipStream_t st,
+                          const BArgs<double>& A, const LArgs& L);
 
 }  // namespace mt

@@ -1,4 +1,5 @@
-// Per-atom evaluation of the minimal Tersoff potential for one candidate.
+// Per-atom evaluation of the Tersoff site energy for one candidate: the
+// minimal potential, or the nine-parameter Tersoff form.
 //
 // One thread owns one atom i with M bonds (compile-time M, padded bonds have
 // f_C = f_C' = 0 and contribute nothing).  For a candidate parameter record it
@@ -19,6 +20,11 @@
 // (the radial term uses sum_k q_jk cos_jk = r^_j . V_j).  Every unordered bond
 // pair (j, k) is visited once in each of the forward (zeta) and backward
 // (gradient) sweeps.
+//
+// The Tersoff form (Sec. II.A Eqs. 2-8 with Eqs. 11-14 for general S) replaces
+// beta (cos - h)^2 by g^T(theta), t^2 by g^T in the P sums, t by g^T'/2 in q_jk,
+// and takes f_R, f_A with their own exponents lambda = alpha sqrt(2S),
+// mu = alpha sqrt(2/S); then D_j = 1/2 [f_C' (f_R - b f_A) + f_C (mu b f_A - lambda f_R)].
 //
 // V is the value type (float, double, or Dual<> for parameter derivatives);
 // S is the geometry type.  The code is written once for all of them.
@@ -89,11 +95,16 @@ struct Geo {
     }
 };
 
-template <typename V, typename S>
+// Decoded parameters of one candidate.  Full selects the Tersoff angular
+// function g^T and independent pair exponents (the nine-parameter form); the
+// minimal potential has g = (cos - h)^2 and lambda = 2 mu.
+template <typename V, typename S, bool Full = false>
 struct Cand {
-    V aL, r0hi, r0lo, D0, twoD0, halpha, beta, hbeta, n, ninv2n, h;
+    static constexpr bool kFull = Full;
+    V aA, aR, r0hi, r0lo, DR, DA, hmu, hlambda, zs, ccs, n, ninv2n, h;
+    V gam, K, d2, Kd2;               // g^T = gam + K t^2 / (d2 + t^2)
     S valid;
-    S aLlo, D0lo, nlo, ninv2nlo;     // low parts for the float64 energy terms
+    S aAlo, aRlo, DRlo, DAlo, nlo, ninv2nlo;   // low parts for the float64 energy terms
 };
 
 // Type of the site energy: float64 for the float path (its energy terms are
@@ -103,44 +114,82 @@ struct EnergyOf { using type = V; };
 template <>
 struct EnergyOf<float> { using type = double; };
 
-template <typename S>
-__device__ __forceinline__ void load_cand(const S* __restrict__ p, Cand<S, S>& c) {
-    c.aL = p[P_AL]; c.r0hi = p[P_R0HI]; c.r0lo = p[P_R0LO]; c.D0 = p[P_D0]; c.twoD0 = p[P_2D0];
-    c.halpha = p[P_HALPHA]; c.beta = p[P_BETA]; c.hbeta = p[P_HBETA];
-    c.n = p[P_N]; c.ninv2n = p[P_NINV2N]; c.h = p[P_H];
-    c.aLlo = p[P_ALLO]; c.D0lo = p[P_D0LO]; c.nlo = p[P_NLO]; c.ninv2nlo = p[P_NINV2NLO];
+// The minimal record leaves the Tersoff-form slots unwritten; its candidate
+// takes lambda = 2 mu and does not read them.
+template <typename S, bool Full>
+__device__ __forceinline__ void load_cand(const S* __restrict__ p, Cand<S, S, Full>& c) {
+    c.aA = p[P_AA]; c.r0hi = p[P_R0HI]; c.r0lo = p[P_R0LO];
+    c.DR = p[P_DR]; c.DA = p[P_DA]; c.hmu = p[P_HMU];
+    c.zs = p[P_ZS]; c.ccs = p[P_CCS]; c.n = p[P_N]; c.ninv2n = p[P_NINV2N]; c.h = p[P_H];
+    c.aAlo = p[P_AALO]; c.DRlo = p[P_DRLO]; c.nlo = p[P_NLO]; c.ninv2nlo = p[P_NINV2NLO];
     c.valid = p[P_VALID];
+    if constexpr (Full) {
+        c.aR = p[P_AR]; c.hlambda = p[P_HLAMBDA]; c.aRlo = p[P_ARLO]; c.DAlo = p[P_DALO];
+        c.gam = p[P_GAM]; c.K = p[P_K]; c.d2 = p[P_D2]; c.Kd2 = p[P_KD2];
+    } else {
+        c.aR = S(2) * c.aA; c.hlambda = S(2) * c.hmu; c.aRlo = S(2) * c.aAlo; c.DAlo = S(2) * c.DRlo;
+        c.gam = S(0); c.K = S(0); c.d2 = S(1); c.Kd2 = S(0);
+    }
 }
 
-// Seeds K parameter directions, parameters Base .. Base + K - 1 of
-// (D0, alpha, r0, beta, n, h).
+// Seeds K parameter directions, parameters Base .. Base + K - 1 of the
+// minimal potential's (D0, alpha, r0, beta, n, h).
 template <int Base, typename S, int K>
-__device__ __forceinline__ void load_cand(const S* __restrict__ p, Cand<Dual<S, K>, S>& c) {
+__device__ __forceinline__ void load_cand(const S* __restrict__ p, Cand<Dual<S, K>, S, false>& c) {
     const S log2e = S(1.4426950408889634);
-    c.aL = dconst<S, K>(p[P_AL]);
+    c.aA = dconst<S, K>(p[P_AA]);
+    c.aR = dconst<S, K>(S(2) * p[P_AA]);
     c.r0hi = dconst<S, K>(p[P_R0HI]);
     c.r0lo = dconst<S, K>(p[P_R0LO]);
-    c.D0 = dconst<S, K>(p[P_D0]);
-    c.twoD0 = dconst<S, K>(p[P_2D0]);
-    c.halpha = dconst<S, K>(p[P_HALPHA]);
-    c.beta = dconst<S, K>(p[P_BETA]);
-    c.hbeta = dconst<S, K>(p[P_HBETA]);
+    c.DR = dconst<S, K>(p[P_DR]);
+    c.DA = dconst<S, K>(p[P_DA]);
+    c.hmu = dconst<S, K>(p[P_HMU]);
+    c.hlambda = dconst<S, K>(S(2) * p[P_HMU]);
+    c.zs = dconst<S, K>(p[P_ZS]);
+    c.ccs = dconst<S, K>(p[P_CCS]);
     c.n = dconst<S, K>(p[P_N]);
     c.ninv2n = dconst<S, K>(p[P_NINV2N]);
     c.h = dconst<S, K>(p[P_H]);
 #pragma unroll
     for (int t = 0; t < K; ++t) {
         switch (Base + t) {
-            case 0: c.D0.d[t] = S(1); c.twoD0.d[t] = S(2); break;
-            case 1: c.aL.d[t] = log2e; c.halpha.d[t] = S(0.5); break;
+            // S = 2: DR = D0, DA = 2 D0, mu = alpha, lambda = 2 alpha
+            case 0: c.DR.d[t] = S(1); c.DA.d[t] = S(2); break;
+            case 1:
+                c.aA.d[t] = log2e; c.hmu.d[t] = S(0.5);
+                c.aR.d[t] = S(2) * log2e; c.hlambda.d[t] = S(1);
+                break;
             case 2: c.r0hi.d[t] = S(1); break;
-            case 3: c.beta.d[t] = S(1); c.hbeta.d[t] = S(0.5); break;
+            case 3: c.zs.d[t] = S(1); c.ccs.d[t] = S(0.5); break;
             // d/dn (-1/(2n)) = 1/(2n^2)
             case 4: c.n.d[t] = S(1); c.ninv2n.d[t] = S(2) * p[P_NINV2N] * p[P_NINV2N]; break;
             case 5: c.h.d[t] = S(1); break;
         }
     }
     c.valid = p[P_VALID];
+}
+
+// Angular function and half its derivative for t = cos(theta) - h:
+// minimal g = t^2, g'/2 = t; Tersoff g^T = gam + K t^2 / (d^2 + t^2),
+// g'/2 = K d^2 t / (d^2 + t^2)^2 (Sec. II.A Eq. 8, written without the
+// cancellation of 1 + c^2/d^2 - c^2/(d^2 + t^2)).
+template <bool Full, typename V, typename P>
+__device__ __forceinline__ V ang_g(const P& p, const V& t) {
+    const V t2 = t * t;
+    if constexpr (Full) return p.gam + (p.K * t2) * drcp(p.d2 + t2);
+    else return t2;
+}
+template <bool Full, typename V, typename P>
+__device__ __forceinline__ void ang_g_dg(const P& p, const V& t, V& gv, V& hg) {
+    const V t2 = t * t;
+    if constexpr (Full) {
+        const V r = drcp(p.d2 + t2);
+        gv = p.gam + (p.K * t2) * r;
+        hg = ((p.Kd2 * t) * r) * r;
+    } else {
+        gv = t2;
+        hg = t;
+    }
 }
 
 // Make the compiler treat the values as changed here (no instruction is
@@ -164,8 +213,8 @@ constexpr int kPairwiseMax = 8;
 // value across passes).  The barriers act on the caller's geometry in place
 // (they change no value), so no second copy of it becomes live.
 template <typename V, typename S, int M, bool Energy64, bool PerBond, bool Fresh = false,
-          typename Sink>
-__device__ __forceinline__ void site_eval_sink(Geo<S, M>& g, const Cand<V, S>& p,
+          bool Full = false, typename Sink>
+__device__ __forceinline__ void site_eval_sink(Geo<S, M>& g, const Cand<V, S, Full>& p,
                                                typename EnergyOf<V>::type& U, Sink&& sink) {
     constexpr int MM = M > 0 ? M : 1;
     if constexpr (Fresh && M > 0) {
@@ -191,9 +240,9 @@ __device__ __forceinline__ void site_eval_sink(Geo<S, M>& g, const Cand<V, S>& p
             for (int k = j + 1; k < M; ++k) {
                 const S c = g.cosjk(j, k, pidx++);
                 const V t = c - p.h;
-                const V t2 = t * t;
-                zeta[j] = zeta[j] + g.fc[k] * t2;
-                zeta[k] = zeta[k] + g.fc[j] * t2;
+                const V gv = ang_g<Full>(p, t);
+                zeta[j] = zeta[j] + g.fc[k] * gv;
+                zeta[k] = zeta[k] + g.fc[j] * gv;
             }
         }
     }
@@ -208,39 +257,52 @@ __device__ __forceinline__ void site_eval_sink(Geo<S, M>& g, const Cand<V, S>& p
     double usum64 = 0.0;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        const V z = zeta[j] * p.beta;
-        // zeta = 0 (no other neighbour inside the cutoff, or all at cos = h):
+        const V z = zeta[j] * p.zs;
+        // zeta = 0 (no other neighbour inside the cutoff, or all at g = 0):
         // zeta^n = 0 exactly, so b = 1 and db/dzeta * zeta^n-terms vanish
         const bool pos = val(z) > S(0);
-        const V zs = dselect(pos, z, vconst<V, S>(S(1)));
-        V e, zn, b;
+        const V zsafe = dselect(pos, z, vconst<V, S>(S(1)));
+        V eA, zn, b;
+        [[maybe_unused]] V eR;
         if constexpr (kE64) {
             const double dl = ((double)g.rhi[j] - (double)p.r0hi) + ((double)g.rlo[j] - (double)p.r0lo);
-            const double e64 = exp2_acc(-(((double)p.aL + (double)p.aLlo) * dl));
+            const double eA64 = exp2_acc(-(((double)p.aA + (double)p.aAlo) * dl));
             const double zn64 =
-                pos ? exp2_acc(((double)p.n + (double)p.nlo) * log2_acc((double)zs)) : 0.0;
+                pos ? exp2_acc(((double)p.n + (double)p.nlo) * log2_acc((double)zsafe)) : 0.0;
             const double b64 = exp2_acc(((double)p.ninv2n + (double)p.ninv2nlo) * log2_acc(1.0 + zn64));
-            const double D0 = (double)p.D0 + (double)p.D0lo;
-            usum64 += (double)g.fc[j] * (D0 * e64 * (e64 - 2.0 * b64));
-            e = (float)e64;
+            const double DR = (double)p.DR + (double)p.DRlo;
+            if constexpr (Full) {
+                const double eR64 = exp2_acc(-(((double)p.aR + (double)p.aRlo) * dl));
+                const double DA = (double)p.DA + (double)p.DAlo;
+                usum64 += (double)g.fc[j] * (DR * eR64 - b64 * (DA * eA64));
+                eR = (float)eR64;
+            } else {
+                // DA = 2 DR, e_R = e_A^2
+                usum64 += (double)g.fc[j] * (DR * eA64 * (eA64 - 2.0 * b64));
+            }
+            eA = (float)eA64;
             zn = (float)zn64;
             b = (float)b64;
         } else {
             const V delta = (g.rhi[j] - p.r0hi) + (g.rlo[j] - p.r0lo);
-            e = dexp2(-(p.aL * delta));
-            zn = dselect(pos, dexp2(p.n * dlog2(zs)), vconst<V, S>(S(0)));
+            eA = dexp2(-(p.aA * delta));
+            if constexpr (Full) eR = dexp2(-(p.aR * delta));
+            zn = dselect(pos, dexp2(p.n * dlog2(zsafe)), vconst<V, S>(S(0)));
             b = dexp2(p.ninv2n * dlog2(S(1) + zn));
         }
         const V onep = S(1) + zn;
-        const V fR = p.D0 * (e * e);
-        const V fA = p.twoD0 * e;
+        V fR;
+        if constexpr (Full) fR = p.DR * eR;
+        else fR = p.DR * (eA * eA);               // e_R = e_A^2
+        const V fA = p.DA * eA;
         const V diff = fR - b * fA;           // one rounding (fused multiply-add)
         const V bfA = b * fA;
         if constexpr (!kE64) usum = usum + g.fc[j] * diff;
-        // D = 1/2 [f_C' (f_R - b f_A) + f_C alpha (b f_A - 2 f_R)]
-        D[j] = g.hfcp[j] * diff + (p.halpha * g.fc[j]) * (bfA - S(2) * fR);
-        // c~ = -beta f_C f_A db/dzeta with db/dzeta = -b zeta^n / (2 zeta (1 + zeta^n))
-        cc[j] = (p.hbeta * g.fc[j]) * (bfA * zn) * drcp(zs * onep);
+        // D = 1/2 [f_C' (f_R - b f_A) + f_C (mu b f_A - lambda f_R)]
+        if constexpr (Full) D[j] = g.hfcp[j] * diff + g.fc[j] * (p.hmu * bfA - p.hlambda * fR);
+        else D[j] = g.hfcp[j] * diff + (p.hmu * g.fc[j]) * (bfA - S(2) * fR);
+        // c~ = -ZS f_C f_A db/dzeta with db/dzeta = -b zeta^n / (2 zeta (1 + zeta^n))
+        cc[j] = (p.ccs * g.fc[j]) * (bfA * zn) * drcp(zsafe * onep);
         // per-bond sweep: keep the scheduler from interleaving all M bonds' chains
         // (about ten live values each)
         if constexpr (PerBond) __builtin_amdgcn_sched_barrier(0);
@@ -264,9 +326,12 @@ __device__ __forceinline__ void site_eval_sink(Geo<S, M>& g, const Cand<V, S>& p
                 if (k == j) continue;
                 const S c = g.ux[j] * g.ux[k] + g.uy[j] * g.uy[k] + g.uz[j] * g.uz[k];
                 const V t = c - p.h;
-                const V q = (cc[j] * g.fc[k] + cc[k] * g.fc[j]) * t;
+                V gv, hg;
+                ang_g_dg<Full>(p, t, gv, hg);
+                const V q = (cc[j] * g.fc[k] + cc[k] * g.fc[j]) * hg;
                 vx = vx + q * g.ux[k]; vy = vy + q * g.uy[k]; vz = vz + q * g.uz[k];
-                pp = pp + (cc[k] * t) * t;
+                if constexpr (Full) pp = pp + cc[k] * gv;
+                else pp = pp + (cc[k] * t) * t;
             }
             const V uv = g.ux[j] * vx + g.uy[j] * vy + g.uz[j] * vz;
             const V rad = D[j] + g.hfcp[j] * pp - uv * g.rinv[j];
@@ -289,12 +354,13 @@ __device__ __forceinline__ void site_eval_sink(Geo<S, M>& g, const Cand<V, S>& p
             for (int k = j + 1; k < M; ++k) {
                 const S c = g.cosjk(j, k, pidx++);
                 const V t = c - p.h;
-                const V t2 = t * t;
-                const V q = (cc[j] * g.fc[k] + cc[k] * g.fc[j]) * t;
+                V gv, hg;
+                ang_g_dg<Full>(p, t, gv, hg);
+                const V q = (cc[j] * g.fc[k] + cc[k] * g.fc[j]) * hg;
                 Vx[j] = Vx[j] + q * g.ux[k]; Vy[j] = Vy[j] + q * g.uy[k]; Vz[j] = Vz[j] + q * g.uz[k];
                 Vx[k] = Vx[k] + q * g.ux[j]; Vy[k] = Vy[k] + q * g.uy[j]; Vz[k] = Vz[k] + q * g.uz[j];
-                Pp[j] = Pp[j] + cc[k] * t2;
-                Pp[k] = Pp[k] + cc[j] * t2;
+                Pp[j] = Pp[j] + cc[k] * gv;
+                Pp[k] = Pp[k] + cc[j] * gv;
             }
         }
     }
@@ -309,8 +375,8 @@ __device__ __forceinline__ void site_eval_sink(Geo<S, M>& g, const Cand<V, S>& p
 }
 
 // The site routine with the bond gradients returned in arrays.
-template <typename V, typename S, int M, bool Energy64 = false>
-__device__ __forceinline__ void site_eval(Geo<S, M>& g, const Cand<V, S>& p,
+template <typename V, typename S, int M, bool Energy64 = false, bool Full = false>
+__device__ __forceinline__ void site_eval(Geo<S, M>& g, const Cand<V, S, Full>& p,
                                           typename EnergyOf<V>::type& U,
                                           V* __restrict__ Gx, V* __restrict__ Gy,
                                           V* __restrict__ Gz) {

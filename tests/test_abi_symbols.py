@@ -20,7 +20,8 @@ def declared_functions():
 
 def test_header_declares_the_three_entry_points():
     names = declared_functions()
-    for n in ("tersoff_eval", "fitness_eval", "fitness_grad", "mt_set_create",
+    for n in ("tersoff_eval", "fitness_eval", "fitness_grad", "tersoff_eval_tf", "fitness_eval_tf",
+              "mt_set_create",
               "mt_set_attach_reference", "mt_set_destroy", "mt_last_error", "mt_autotune"):
         assert n in names
 
@@ -60,4 +61,7 @@ def test_argument_errors_without_gpu():
     assert lib.mt_set_create(ctypes.byref(h), 2, off2, ctypes.c_void_p(1), ctypes.c_void_p(1),
                              2.8, 3.2, 16, None) == L.MT_EINVAL
     assert lib.tersoff_eval(None, None, 1, 0, 0, None, None, None, None, None, None, None) == L.MT_EINVAL
+    assert lib.tersoff_eval_tf(None, None, 1, 0, 0, None, None, None, None, None, None, None) == L.MT_EINVAL
+    w = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    assert lib.fitness_eval_tf(None, None, 1, w, 0, 0, None, None) == L.MT_EINVAL
     assert lib.mt_set_destroy(None) == L.MT_OK

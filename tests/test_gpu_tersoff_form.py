@@ -1,0 +1,173 @@
+"""GPU parity of the nine-parameter Tersoff form (Sec. II.A Eqs. 2-9 with
+Tersoff's angular function, Eq. 8, and Eqs. 11-14 at a free slope S) against
+the oracle, through tersoff_eval_tf and fitness_eval_tf.
+
+Structures: strained 64-atom diamond cells, random packings with coordination
+up to 12 (the one-bond-at-a-time backward sweep above 8 neighbours), small
+clusters (dimer, trimers, isolated atom) and a 600-atom packing (two-pass
+path).  Parameters: uniform inside the nine-parameter box.  Tolerances as in
+test_gpu_parity: float64 1e-10 relative to the quantity's scale; float32
+arithmetic 1e-6 eV/atom energy, 1e-4 eV/A force, 1e-5 eV/atom virial; fitness
+1e-10 (float64) and 1e-5 (float32) relative.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import tersoff as T
+
+pytestmark = pytest.mark.gpu
+
+R1, R2 = 2.8, 3.2
+BOX = np.eye(3) * 20.0
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_11474_amd import api as A
+    return A
+
+
+def mixed_set(with_large):
+    g = rng(61)
+    c = np.array([10.0, 10.0, 10.0])
+    tri = c + 2.4 * np.array([[0, 0, 0], [1, 0, 0], [0.5, np.sqrt(3) / 2, 0]])
+    line = c + np.array([[0, 0, 0], [2.3, 0, 0], [4.6, 0, 0]])
+    structs = W.strained_diamond_cells(62, 2) + [
+        W.random_packing(g, 40), W.random_packing(g, 90), W.random_packing(g, 9),
+        (c[None], BOX), (c + [[0, 0, 0], [2.35, 0, 0]], BOX), (c + [[0, 0, 0], [0, 3.0, 0]], BOX),
+        (tri, BOX), (line, BOX)]
+    if with_large:
+        structs.append(W.random_packing(g, 600))
+    return W.make_set(structs)
+
+
+def check_eval(out, s, X, precision):
+    E, F, Wv, Wi = (out[k].cpu().numpy() for k in ("E", "F", "W", "Wi"))
+    sizes = s.sizes().astype(float)
+    for c, x in enumerate(X):
+        print("candidate", c, precision, flush=True)
+        ref = T.evaluate_set(s, x, R1, R2, atom_virial=True)
+        if precision == "fp64":
+            assert np.abs(E[c] - ref["E"]).max() <= 1e-10 * max(np.abs(ref["E"]).max(), 1e-2)
+            assert np.abs(F[c] - ref["F"]).max() <= 1e-10 * max(np.abs(ref["F"]).max(), 1e-12) + 1e-12
+            assert np.abs(Wv[c] - ref["W6"]).max() <= 1e-10 * max(np.abs(ref["W6"]).max(), 1e-2)
+            assert np.abs(Wi[c] - ref["Wi"]).max() <= 1e-10 * max(np.abs(ref["Wi"]).max(), 1e-2)
+        else:
+            assert np.abs(E[c] / sizes - ref["E"] / sizes).max() <= 1e-6
+            assert np.abs(F[c] - ref["F"]).max() <= 1e-4
+            assert np.abs(Wv[c] / sizes[:, None] - ref["W6"] / sizes[:, None]).max() <= 1e-5
+            assert np.abs(Wi[c] - ref["Wi"]).max() <= 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_tersoff_form_eval_matches_oracle(api, precision):
+    s = mixed_set(with_large=True)
+    ts = api.from_structures(s)
+    st = ts.stats()
+    assert st["n_large"] == 1 and st["max_coordination"] > 8
+    X = W.draw_params_full(rng(63), 3)
+    out = ts.tersoff_eval(X, precision=precision, atom_virial=True)
+    check_eval(out, s, X, precision)
+    ts.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_tersoff_form_fitness_matches_oracle_and_plain(api, precision):
+    s = mixed_set(with_large=True)
+    hidden = W.draw_params_full(rng(64), 1)[0]
+    refs = T.reference_data(s, hidden, R1, R2)
+    ts = api.from_structures(s)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    X = W.draw_params_full(rng(65), 8)
+    weights = (1.0, 0.7, 1.3)
+    Zb = ts.fitness(X, weights, precision=precision).cpu().numpy()
+    Zp = ts.fitness(X, weights, precision=precision, schedule="plain").cpu().numpy()
+    idx = [0, 3, 7]
+    Zo = T.fitness(s, X[idx], refs, weights, topology=T.topology(s, R2))
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    assert np.abs(Zb[idx] - Zo).max() <= tol * np.abs(Zo).max()
+    if precision == "fp64":
+        assert np.array_equal(Zb, Zp)
+    else:
+        assert np.abs(Zb - Zp).max() <= 1e-5 * np.abs(Zb).max()
+    # the hidden set itself: Z = 0 up to the precision's rounding
+    Zh = ts.fitness(hidden[None], weights, precision=precision).cpu().numpy()
+    assert Zh[0, 0] <= (1e-12 if precision == "fp64" else 1e-5)
+    ts.close()
+
+
+def test_graphs_of_the_two_forms_are_kept_apart(api):
+    """Alternating minimal and Tersoff-form fitness calls (captured graphs are
+    keyed by form) give the same bits as each form alone."""
+    import torch
+    wl = W.config2(n_struct=6, pop=8)
+    refs = T.reference_data(wl.structs, wl.hidden_x, R1, R2)
+    ts = api.from_structures(wl.structs)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    xm = torch.as_tensor(wl.population, device="cuda")
+    xf = torch.as_tensor(W.draw_params_full(rng(66), 8), device="cuda")
+    zm = ts.fitness(xm).clone()
+    zf = ts.fitness(xf).clone()
+    for _ in range(3):
+        assert torch.equal(ts.fitness(xm), zm)
+        assert torch.equal(ts.fitness(xf), zf)
+    zo = T.fitness(wl.structs, xf.cpu().numpy()[:2], refs, topology=T.topology(wl.structs, R2))
+    assert np.abs(zf.cpu().numpy()[:2] - zo).max() <= 1e-5 * np.abs(zo).max()
+    ts.close()
+
+
+def test_limit_of_the_tersoff_form_is_the_minimal_potential(api):
+    """Sec. II.B: with S = 2, c = 10 d^3 and gamma = beta d^4 / c^2, g^T tends to
+    beta (cos - h)^2 as d grows; the GPU energies of the two forms (float64)
+    converge as 1 / d^2, as in the oracle."""
+    s = W.make_set(W.strained_diamond_cells(67, 1) + [W.random_packing(rng(68), 30)])
+    ts = api.from_structures(s)
+    for x in [np.array(W.TABLE2_X)] + list(W.draw_params(rng(69), 2)):
+        e_min = ts.tersoff_eval(x[None], precision="fp64")["E"].cpu().numpy()[0]
+        errs = []
+        for dd in (10.0, 100.0, 1000.0):
+            xf = W.minimal_as_full(x, dd, 10.0 * dd ** 3)
+            e = ts.tersoff_eval(xf[None], precision="fp64")["E"].cpu().numpy()[0]
+            errs.append(np.abs((e - e_min) / e_min).max())
+        assert errs[0] > 50 * errs[1] > 2500 * errs[2]
+        assert errs[2] < 1e-5
+    ts.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_out_of_domain_candidates_are_nan_and_isolated(api, precision):
+    s = mixed_set(with_large=False)
+    hidden = W.draw_params_full(rng(70), 1)[0]
+    refs = T.reference_data(s, hidden, R1, R2)
+    ts = api.from_structures(s)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    X = W.draw_params_full(rng(71), 6)
+    bad = X.copy()
+    bad[0, 3] = 1.0            # S = 1
+    bad[1, 7] = 0.0            # d = 0
+    bad[2, 5] = 0.0            # n = 0
+    bad[3, 4] = -0.1           # gamma < 0
+    bad[4, 0] = np.nan
+    Z = ts.fitness(bad, precision=precision).cpu().numpy()
+    assert np.isnan(Z[:5]).all()
+    Z5 = ts.fitness(X[5:6], precision=precision).cpu().numpy()
+    assert np.array_equal(Z[5], Z5[0])
+    E = ts.tersoff_eval(bad, precision=precision)["E"].cpu().numpy()
+    assert np.isnan(E[:5]).all() and np.isfinite(E[5]).all()
+    ts.close()
+
+
+def test_gradient_is_for_the_minimal_potential_only(api):
+    s = mixed_set(with_large=False)
+    ts = api.from_structures(s)
+    with pytest.raises(ValueError):
+        ts.fitness_grad(W.draw_params_full(rng(72), 2))
+    ts.close()

@@ -184,7 +184,7 @@ def random_packing(rng: np.random.Generator, n: int, rho: float = RHO_SI,
 class Workload:
     name: str
     structs: StructureSet
-    population: np.ndarray                 # [P, 6] parameter sets
+    population: np.ndarray                 # [P, 6] (minimal) or [P, 9] (Tersoff form) parameter sets
     hidden_x: Optional[np.ndarray] = None  # parameters the reference data come from
     velocities: Optional[np.ndarray] = None
     R1: float = TABLE2_R1
@@ -219,6 +219,18 @@ def config2(struct_seed: int = 3, hidden_seed: int = 4, pop_seed: int = 5,
     x = draw_params(np.random.Generator(np.random.PCG64(pop_seed)), pop)
     return Workload(f"config2: GA fitness batch, {pop} candidates x {n_struct} strained "
                     "64-atom diamond cells", structs, x, hidden_x=hidden,
+                    seeds={"structures": struct_seed, "hidden": hidden_seed, "population": pop_seed})
+
+
+def config2_tersoff_form(struct_seed: int = 3, hidden_seed: int = 11, pop_seed: int = 12,
+                         n_struct: int = 100, pop: int = 200) -> Workload:
+    """config 2's structures with nine-parameter Tersoff-form candidates and a
+    hidden nine-parameter set (Sec. II.A Eq. 8 with a free slope S)."""
+    structs = make_set(strained_diamond_cells(struct_seed, n_struct), ["diamond"] * n_struct)
+    hidden = draw_params_full(np.random.Generator(np.random.PCG64(hidden_seed)), 1)[0]
+    x = draw_params_full(np.random.Generator(np.random.PCG64(pop_seed)), pop)
+    return Workload(f"config2-tf: GA fitness batch, Tersoff form (9 parameters), {pop} candidates "
+                    f"x {n_struct} strained 64-atom diamond cells", structs, x, hidden_x=hidden,
                     seeds={"structures": struct_seed, "hidden": hidden_seed, "population": pop_seed})
 
 

@@ -189,8 +189,7 @@ int fitness_eval(mt_set* set, const double* x, int P, const double* w, int preci
 /*
  * fitness_eval for the nine-parameter Tersoff form (the Sec. III.B fitness of
  * the Sec. II.A potential): x is device [P][9] as described at the top of this
- * file; w, Z, schedule, precision and errors as for fitness_eval.  There is no
- * gradient entry point for this form.
+ * file; w, Z, schedule, precision and errors as for fitness_eval.
  */
 int fitness_eval_tf(mt_set* set, const double* x, int P, const double* w, int precision,
                     int schedule, double* Z, void* stream);
@@ -206,6 +205,15 @@ int fitness_eval_tf(mt_set* set, const double* x, int P, const double* w, int pr
  */
 int fitness_grad(mt_set* set, const double* x, int P, const double* w, int precision,
                  double* Z, double* dZdx, void* stream);
+
+/*
+ * fitness_grad for the nine-parameter Tersoff form: x is device [P][9] as
+ * described at the top of this file and dZdx is device [P][9], the derivative
+ * with respect to D0, alpha, r0, S, gamma, n, c, d, h; limits and errors as for
+ * fitness_grad.
+ */
+int fitness_grad_tf(mt_set* set, const double* x, int P, const double* w, int precision,
+                    double* Z, double* dZdx, void* stream);
 
 /*
  * Choose launch shapes (block size, candidate tile, schedule) for this set

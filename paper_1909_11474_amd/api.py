@@ -199,16 +199,18 @@ class TersoffSet:
         return FitnessCall(self, x, Z, weights, precision, schedule)
 
     def fitness_grad(self, x, weights=(1.0, 1.0, 1.0), precision="fp32"):
-        """(Z [P, 4], dZ/dx [P, 6]) as device tensors (minimal potential only)."""
-        xt = self._x(x, widths=(6,))
-        P = xt.shape[0]
+        """(Z [P, 4], dZ/dx [P, 6]) as device tensors; for Tersoff-form x [P, 9]
+        (fitness_grad_tf) dZ/dx is [P, 9]."""
+        xt = self._x(x)
+        P, nx = xt.shape
         w = (ctypes.c_double * 3)(*[float(v) for v in weights])
+        name = "fitness_grad_tf" if nx == 9 else "fitness_grad"
         with torch.cuda.device(self.device):
             Z = torch.empty(P, 4, dtype=torch.float64, device=self.device)
-            G = torch.empty(P, 6, dtype=torch.float64, device=self.device)
-            rc = self._lib.fitness_grad(self._handle, _ptr(xt), P, w, _prec(precision), _ptr(Z),
-                                        _ptr(G), self._stream())
-        L.check(rc, "fitness_grad")
+            G = torch.empty(P, nx, dtype=torch.float64, device=self.device)
+            rc = getattr(self._lib, name)(self._handle, _ptr(xt), P, w, _prec(precision), _ptr(Z),
+                                          _ptr(G), self._stream())
+        L.check(rc, name)
         return Z, G
 
     def profile(self, enable: bool = True):
@@ -265,7 +267,7 @@ def from_structures(structs, R1: float = 2.8, R2: float = 3.2, max_nbr: int = L.
 
 
 class TersoffFitness(torch.autograd.Function):
-    """Z(x) for a population x [P, 6] as a differentiable function.
+    """Z(x) for a population x [P, 6] (or Tersoff-form [P, 9]) as a differentiable function.
 
     forward: fitness_eval, or fitness_grad when x requires a gradient;
     backward: grad_Z[:, None] * dZ/dx."""

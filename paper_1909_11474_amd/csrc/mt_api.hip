@@ -336,8 +336,10 @@ int fitness_eval_tf(mt_set* set, const double* x, int P, const double* w, int pr
     return fitness_impl(set, x, 1, P, w, precision, schedule, Z, stream);
 }
 
-int fitness_grad(mt_set* set, const double* x, int P, const double* w, int precision, double* Z,
-                 double* dZdx, void* stream) {
+}  // extern "C"
+
+static int grad_impl(mt_set* set, const double* x, int form, int P, const double* w,
+                     int precision, double* Z, double* dZdx, void* stream) {
     TRY(check_fitness(set, x, P, w, precision, Z));
     if (!dZdx) return fail(MT_EINVAL, "dZdx must not be NULL");
     if (set->n_large > 0)
@@ -348,10 +350,22 @@ int fitness_grad(mt_set* set, const double* x, int P, const double* w, int preci
                                    std::to_string(MT_MAX_GRAD_NBR));
     hipStream_t st = (hipStream_t)stream;
     TRY(ensure_workspace(set, P, kNVFit));
-    TRY(fitness_sequence(set, x, 0, P, w, precision, MT_BATCHED, Z, st));
+    TRY(fitness_sequence(set, x, form, P, w, precision, MT_BATCHED, Z, st));
     const LaunchCfg cfg = cfg_for(set, P, precision);
     TRY(launch_adjoint(set, cfg, P, precision, w, Z, st));
     return launch_finalize_grad(set, P, Z, dZdx, st);
+}
+
+extern "C" {
+
+int fitness_grad(mt_set* set, const double* x, int P, const double* w, int precision, double* Z,
+                 double* dZdx, void* stream) {
+    return grad_impl(set, x, 0, P, w, precision, Z, dZdx, stream);
+}
+
+int fitness_grad_tf(mt_set* set, const double* x, int P, const double* w, int precision,
+                    double* Z, double* dZdx, void* stream) {
+    return grad_impl(set, x, 1, P, w, precision, Z, dZdx, stream);
 }
 
 int mt_profile_enable(mt_set* set, int enable) {

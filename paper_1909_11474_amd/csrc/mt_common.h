@@ -40,6 +40,7 @@ constexpr int kMaxBatched = 512;   // largest structure of the batched kernel
 constexpr int kNVFit = 8;          // partial sums per slot: E, W6, |F - F*|^2
 constexpr int kNVEval = 16;        // E, W6, |F-F*|^2, J3, unused
 constexpr int kNVGrad = 8;         // dZ/dx (6), unused (2)
+constexpr int kNVGradTF = 16;      // Tersoff form: dZ/dx (9), unused (7)
 constexpr int kNParam = 24;        // per-candidate decoded parameter record
 
 // Decoded parameter record (float or double), filled per work item in LDS.

@@ -217,26 +217,28 @@ __global__ __launch_bounds__(256) void k_grad_coef(FinArgs F) {
     }
 }
 
+// dZ/dx [P][nx], nx = 6 (minimal) or 9 (Tersoff form).
 __global__ __launch_bounds__(256) void k_finalize_grad(FinArgs F, double* dZdx) {
-    __shared__ double sh[6][256];
+    __shared__ double sh[9][256];
     const int c = blockIdx.x;
     const SetDev& d = F.set;
-    double acc[6] = {0, 0, 0, 0, 0, 0};
+    const int nx = F.full ? 9 : 6;
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int sl = threadIdx.x; sl < d.nslots; sl += blockDim.x) {
         const double* p = F.partial + ((size_t)c * d.nslots + sl) * F.nv;
-        for (int k = 0; k < 6; ++k) acc[k] += p[k];
+        for (int k = 0; k < nx; ++k) acc[k] += p[k];
     }
-    for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] = acc[k];
+    for (int k = 0; k < 9; ++k) sh[k][threadIdx.x] = acc[k];
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o)
-            for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + o];
+            for (int k = 0; k < 9; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         const bool ok = cand_valid(F.x, c, F.full);
         const double nan = __longlong_as_double(0x7ff8000000000000ll);
-        for (int k = 0; k < 6; ++k) dZdx[6 * c + k] = ok ? sh[k][0] : nan;
+        for (int k = 0; k < nx; ++k) dZdx[(size_t)nx * c + k] = ok ? sh[k][0] : nan;
     }
 }
 
@@ -308,16 +310,19 @@ FinArgs make_fin(mt_set* set, int nv, const double* partial) {
 
 bool family_f64(int fam) {
     return fam == FAM_FIT64 || fam == FAM_EVAL64 || fam == FAM_ADJ64 || fam == FAM_FIT64F ||
-           fam == FAM_EVAL64F;
+           fam == FAM_EVAL64F || fam == FAM_ADJ64F;
 }
 bool family_fit(int fam) {
     return fam == FAM_FIT32 || fam == FAM_FIT64 || fam == FAM_FIT32F || fam == FAM_FIT64F;
 }
 bool family_full(int fam) {
-    return fam == FAM_FIT32F || fam == FAM_EVAL32F || fam == FAM_FIT64F || fam == FAM_EVAL64F;
+    return fam == FAM_FIT32F || fam == FAM_EVAL32F || fam == FAM_FIT64F || fam == FAM_EVAL64F ||
+           fam == FAM_ADJ32F || fam == FAM_ADJ64F;
 }
 int family_elem(int fam) { return family_f64(fam) ? 8 : 4; }
-bool family_adjoint(int fam) { return fam == FAM_ADJ32 || fam == FAM_ADJ64; }
+bool family_adjoint(int fam) {
+    return fam == FAM_ADJ32 || fam == FAM_ADJ64 || fam == FAM_ADJ32F || fam == FAM_ADJ64F;
+}
 
 // LDS of one item: parameter records, bond-gradient exchange slots (4 values
 // each) and, for the adjoint, the force-residual exchange.
@@ -345,6 +350,8 @@ hipError_t launch_family(int fam, int mc, dim3 g, dim3 b, size_t lds, hipStream_
         case FAM_EVAL32F: return launch_eval32f(mc, g, b, lds, st, Af, e0, e1);
         case FAM_FIT64F: return launch_fit64f(mc, g, b, lds, st, Ad, e0, e1);
         case FAM_EVAL64F: return launch_eval64f(mc, g, b, lds, st, Ad, e0, e1);
+        case FAM_ADJ32F: return launch_adj32f(mc, g, b, lds, st, Af, e0, e1);
+        case FAM_ADJ64F: return launch_adj64f(mc, g, b, lds, st, Ad, e0, e1);
     }
     return hipErrorInvalidValue;
 }
@@ -373,6 +380,8 @@ const std::vector<int>& family_classes(int fam) {
         {4, 16},             // EVAL32F
         {4, 16},             // FIT64F
         {4, 16},             // EVAL64F
+        {4, 12},             // ADJ32F
+        {4, 12},             // ADJ64F
     };
     return k[fam];
 }
@@ -710,13 +719,11 @@ static int launch_grad_coef(mt_set* set, int P, const double* w, const double* Z
 
 static int adjoint_common(mt_set* set, const LaunchCfg& cfg, int P, int precision, const double* w,
                           const double* Z, hipStream_t st) {
-    if (set->cur_form != 0) {
-        set_error("the fitness gradient covers the minimal potential only");
-        return MT_EINVAL;
-    }
     TRY_RC(launch_grad_coef(set, P, w, Z, st));
-    HIPCHECK(set->partial2.reserve(sizeof(double) * kNVGrad * (size_t)P * set->nslots));
-    const int fam = precision == MT_FP64 ? FAM_ADJ64 : FAM_ADJ32;
+    const int nv = set->cur_form ? kNVGradTF : kNVGrad;
+    HIPCHECK(set->partial2.reserve(sizeof(double) * nv * (size_t)P * set->nslots));
+    const bool f64 = precision == MT_FP64;
+    const int fam = set->cur_form ? (f64 ? FAM_ADJ64F : FAM_ADJ32F) : (f64 ? FAM_ADJ64 : FAM_ADJ32);
     ItemPlan* plan = get_plan(set, P, cfg, fam);
     if (!plan) {
         set_error("could not build the adjoint work list");
@@ -729,8 +736,8 @@ static int adjoint_common(mt_set* set, const LaunchCfg& cfg, int P, int precisio
                   " atoms) does not fit one block's LDS in this precision");
         return MT_EINVAL;
     }
-    BArgs<float> Af = make_args<float>(set, set->partial2.as<double>(), kNVGrad);
-    BArgs<double> Ad = make_args<double>(set, set->partial2.as<double>(), kNVGrad);
+    BArgs<float> Af = make_args<float>(set, set->partial2.as<double>(), nv);
+    BArgs<double> Ad = make_args<double>(set, set->partial2.as<double>(), nv);
     Af.coef = Ad.coef = set->zwork.as<double>();
     return run_plan(set, plan, cfg, fam, Af, Ad, 1, st);
 }
@@ -748,7 +755,7 @@ int launch_adjoint_plain(mt_set* set, int P, int precision, const double* w, con
 
 int launch_finalize_grad(mt_set* set, int P, const double* Z, double* dZdx, hipStream_t st) {
     (void)Z;
-    FinArgs F = make_fin(set, kNVGrad, set->partial2.as<double>());
+    FinArgs F = make_fin(set, set->cur_form ? kNVGradTF : kNVGrad, set->partial2.as<double>());
     hipLaunchKernelGGL(k_finalize_grad, dim3(P), dim3(256), 0, st, F, dZdx);
     HIPCHECK(hipGetLastError());
     return MT_OK;

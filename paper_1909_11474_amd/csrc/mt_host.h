@@ -64,11 +64,10 @@ struct ItemPlan {             // uploaded work lists for one (P, launch shape, k
 };
 
 // Kernel families: precision x (fitness, energy/force/virial, adjoint) for the
-// minimal potential, and precision x (fitness, energy/force/virial) for the
-// nine-parameter Tersoff form (suffix F).
+// minimal potential and (suffix F) for the nine-parameter Tersoff form.
 enum Family {
     FAM_FIT32 = 0, FAM_EVAL32, FAM_FIT64, FAM_EVAL64, FAM_ADJ32, FAM_ADJ64,
-    FAM_FIT32F, FAM_EVAL32F, FAM_FIT64F, FAM_EVAL64F, NFAM
+    FAM_FIT32F, FAM_EVAL32F, FAM_FIT64F, FAM_EVAL64F, FAM_ADJ32F, FAM_ADJ64F, NFAM
 };
 
 struct GraphKey {             // what a captured fitness graph depends on

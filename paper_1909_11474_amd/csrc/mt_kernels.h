@@ -433,26 +433,27 @@ void k_plain(BArgs<S> A) {
 // Adjoint kernel: dZ/dx of the fitness.  For candidate c and structure s,
 //   dZ/dx|_s = sum_i [ k_e U_i' - sum_j G_ij' . delta_ij ],
 //   delta_ij = k_f (a_j - a_i) + C_s r_ij,   a = F - F*,
-// where ' is the derivative with respect to the six parameters (forward-mode
-// dual numbers), k_e = w_e (e_s - e*_s)/(N_s Z_e Q_e), k_f = w_f/(Z_f Q_f) and
+// where ' is the derivative with respect to the parameters (six, or nine for
+// the Tersoff form; forward-mode dual numbers), k_e = w_e (e_s - e*_s)/(N_s Z_e Q_e), k_f = w_f/(Z_f Q_f) and
 // C_s = w_v/(N_s Z_v Q_v) times the symmetric matrix of virial residuals (off
 // diagonals halved).  These follow from dF_i/dx = -d/dx dE/dr_i and
 // dW/dx = -sum r_ij (x) dG_ij/dx.
 //
 // Per candidate: a plain pass gives the force residuals a_i, shared through
-// LDS; then dual passes over K of the six parameters at a time contract each
+// LDS; then dual passes over K of the parameters at a time contract each
 // G_ij' with delta_ij as soon as the site routine emits it, so no bond
 // gradient derivative is held across the exchange.
 // ---------------------------------------------------------------------------
 
-// Tangents per dual pass: all six in one pass for small coordination, three
-// (two passes) where six would not fit in registers.
+// Tangents per dual pass: six for small coordination (one pass for the six
+// minimal parameters; six and three for the nine of the Tersoff form), three
+// where six would not fit in registers.
 template <typename S, int M>
 struct AdjointTangents {
     static constexpr int value = (M <= 4 && sizeof(S) == 4) ? 6 : 3;
 };
 
-template <typename S, int M>
+template <typename S, int M, bool Full = false>
 __device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, const ItemCtx& x,
                                             unsigned char* __restrict__ lds) {
     const SetDev& d = A.set;
@@ -464,6 +465,7 @@ __device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, c
     g.load(geom_of<S>(d), N, x.atom, x.active);
     constexpr int MM = M > 0 ? M : 1;
     constexpr int K = AdjointTangents<S, M>::value;
+    constexpr int NX = Form<Full>::nx;
     int rv[MM], jl[MM];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
@@ -483,7 +485,7 @@ __device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, c
         // plain pass: force residual of this atom
         S ax = S(0), ay = S(0), az = S(0);
         {
-            Cand<S, S> pp;
+            Cand<S, S, Full> pp;
             load_cand(prec, pp);
             double U0;
             S Gx[MM], Gy[MM], Gz[MM];
@@ -506,15 +508,17 @@ __device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, c
         const S ke = (S)cf[0], kf = (S)cf[1];
         const S cxx = (S)cf[2], cyy = (S)cf[3], czz = (S)cf[4];
         const S cyz = (S)cf[5], czx = (S)cf[6], cxy = (S)cf[7];
-        S phi[6];
-        // dual passes
-        auto pass = [&](auto base_c) {
+        S phi[NX];
+        // dual passes over KK parameters from Base
+        auto pass = [&](auto base_c, auto k_c) {
             constexpr int Base = decltype(base_c)::value;
-            Cand<Dual<S, K>, S> p;
-            load_cand<Base>(prec, p);
-            Dual<S, K> U;
-            site_eval_sink<Dual<S, K>, S, M, false, true, true>(
-                g, p, U, [&](int m, const Dual<S, K>& gx, const Dual<S, K>& gy, const Dual<S, K>& gz) {
+            constexpr int KK = decltype(k_c)::value;
+            Cand<Dual<S, KK>, S, Full> p;
+            if constexpr (Full) load_cand<Base>(prec, A.x + (size_t)NX * c, p);
+            else load_cand<Base>(prec, p);
+            Dual<S, KK> U;
+            site_eval_sink<Dual<S, KK>, S, M, false, true, true>(
+                g, p, U, [&](int m, const Dual<S, KK>& gx, const Dual<S, KK>& gy, const Dual<S, KK>& gz) {
                     // a fresh read in every pass (a reused one would stay live across passes)
                     int jm = jl[m];
                     asm volatile("" : "+v"(jm));
@@ -524,33 +528,41 @@ __device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, c
                     const S ey = kf * (aj.y - ay) + cxy * dx + cyy * dy + cyz * dz;
                     const S ez = kf * (aj.z - az) + czx * dx + cyz * dy + czz * dz;
 #pragma unroll
-                    for (int t = 0; t < K; ++t) phi[Base + t] -= gx.d[t] * ex + gy.d[t] * ey + gz.d[t] * ez;
+                    for (int t = 0; t < KK; ++t) phi[Base + t] -= gx.d[t] * ex + gy.d[t] * ey + gz.d[t] * ez;
                 });
 #pragma unroll
-            for (int t = 0; t < K; ++t) phi[Base + t] += ke * U.d[t];
+            for (int t = 0; t < KK; ++t) phi[Base + t] += ke * U.d[t];
         };
+        using I = std::integral_constant<int, 0>;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) phi[k] = S(0);
-        pass(std::integral_constant<int, 0>{});
-        if constexpr (K <= 3) pass(std::integral_constant<int, K>{});
-        if constexpr (K <= 2) pass(std::integral_constant<int, 2 * K>{});
-        if constexpr (K == 1) {
-            pass(std::integral_constant<int, 3>{});
-            pass(std::integral_constant<int, 4>{});
-            pass(std::integral_constant<int, 5>{});
+        for (int k = 0; k < NX; ++k) phi[k] = S(0);
+        static_assert(K == 3 || K == 6, "tangent blocks of 3 or 6");
+        if constexpr (K == 6) {
+            pass(I{}, std::integral_constant<int, 6>{});
+            if constexpr (Full) pass(std::integral_constant<int, 6>{}, std::integral_constant<int, 3>{});
+        } else {
+            pass(I{}, std::integral_constant<int, 3>{});
+            pass(std::integral_constant<int, 3>{}, std::integral_constant<int, 3>{});
+            if constexpr (Full) pass(std::integral_constant<int, 6>{}, std::integral_constant<int, 3>{});
         }
         exchange_sync(x.block_sync);
         double v[8];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) v[k] = (double)phi[k];
-        v[6] = v[7] = 0.0;
-        store_group(v, x, group_ok, A.partial, d.nslots, A.nv, c, 0, 0x3f);
+        for (int k = 0; k < 8; ++k) v[k] = k < NX ? (double)phi[k < NX ? k : 0] : 0.0;
+        store_group(v, x, group_ok, A.partial, d.nslots, A.nv, c, 0, Full ? 0xff : 0x3f);
+        if constexpr (Full) {
+            double u[8];
+            u[0] = (double)phi[8];
+#pragma unroll
+            for (int k = 1; k < 8; ++k) u[k] = 0.0;
+            store_group(u, x, group_ok, A.partial, d.nslots, A.nv, c, 8, 0x01);
+        }
     }
 }
 
-template <typename S, int MC>
+template <typename S, int MC, bool Full>
 __device__ __forceinline__ void adjoint_item(const BArgs<S>& A, const Item& it, unsigned char* lds) {
-    decode_item<S>(A, it, lds);
+    decode_item<S, Full>(A, it, lds);
     const ItemCtx x = item_ctx(A.set, it);
     const int Mi = x.active ? A.set.nnb[x.atom] : -1;
     const int Mw = wave_max_int(Mi);
@@ -559,17 +571,17 @@ __device__ __forceinline__ void adjoint_item(const BArgs<S>& A, const Item& it, 
         return;
     }
     dispatch_m<ClassLo<MC>::value, MC>(Mw, [&](auto mv) {
-        run_adjoint<S, decltype(mv)::value>(A, it, x, lds);
+        run_adjoint<S, decltype(mv)::value, Full>(A, it, x, lds);
     });
 }
 
-template <typename S, int MC>
+template <typename S, int MC, bool Full = false>
 __global__ __launch_bounds__(512) void k_adjoint(BArgs<S> A) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int b0 = A.bin_off[blockIdx.x], b1 = A.bin_off[blockIdx.x + 1];
     for (int i = b0; i < b1; ++i) {
         const Item it = A.items[i];
-        adjoint_item<S, MC>(A, it, lds_raw);
+        adjoint_item<S, MC, Full>(A, it, lds_raw);
         __syncthreads();
     }
 }
@@ -735,6 +747,10 @@ hipError_t launch_adj32(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, cons
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_adj64(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<double>& A,
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_adj32f(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<float>& A,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_adj64f(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<double>& A,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Tersoff-form (nine-parameter) batched families.
 hipError_t launch_fit32f(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<float>& A,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);

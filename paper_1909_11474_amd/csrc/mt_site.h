@@ -169,6 +169,62 @@ __device__ __forceinline__ void load_cand(const S* __restrict__ p, Cand<Dual<S, 
     c.valid = p[P_VALID];
 }
 
+// Seeds K parameter directions, parameters Base .. Base + K - 1 of the
+// Tersoff form's (D0, alpha, r0, S, gamma, n, c, d, h): values from the record
+// p, tangents of the record's fields from the candidate's x (float64):
+//   DR = D0/(S-1), DA = S D0/(S-1), mu = alpha sqrt(2/S), lambda = alpha sqrt(2S),
+//   K = gamma c^2/d^2, d^2, K d^2 = gamma c^2, -1/(2n).
+template <int Base, typename S, int K>
+__device__ __forceinline__ void load_cand(const S* __restrict__ p, const double* __restrict__ x,
+                                          Cand<Dual<S, K>, S, true>& c) {
+    const double log2e = 1.4426950408889634;
+    c.aA = dconst<S, K>(p[P_AA]);
+    c.aR = dconst<S, K>(p[P_AR]);
+    c.r0hi = dconst<S, K>(p[P_R0HI]);
+    c.r0lo = dconst<S, K>(p[P_R0LO]);
+    c.DR = dconst<S, K>(p[P_DR]);
+    c.DA = dconst<S, K>(p[P_DA]);
+    c.hmu = dconst<S, K>(p[P_HMU]);
+    c.hlambda = dconst<S, K>(p[P_HLAMBDA]);
+    c.zs = dconst<S, K>(p[P_ZS]);
+    c.ccs = dconst<S, K>(p[P_CCS]);
+    c.n = dconst<S, K>(p[P_N]);
+    c.ninv2n = dconst<S, K>(p[P_NINV2N]);
+    c.h = dconst<S, K>(p[P_H]);
+    c.gam = dconst<S, K>(p[P_GAM]);
+    c.K = dconst<S, K>(p[P_K]);
+    c.d2 = dconst<S, K>(p[P_D2]);
+    c.Kd2 = dconst<S, K>(p[P_KD2]);
+    const double D0 = x[0], al = x[1], Sl = x[3], gam = x[4], n = x[5], cc = x[6], d = x[7];
+    const double rs = sqrt(2.0 / Sl), rl = sqrt(2.0 * Sl), sm1 = Sl - 1.0;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        switch (Base + t) {
+            case 0: c.DR.d[t] = (S)(1.0 / sm1); c.DA.d[t] = (S)(Sl / sm1); break;
+            case 1:
+                c.aA.d[t] = (S)(rs * log2e); c.aR.d[t] = (S)(rl * log2e);
+                c.hmu.d[t] = (S)(0.5 * rs); c.hlambda.d[t] = (S)(0.5 * rl);
+                break;
+            case 2: c.r0hi.d[t] = S(1); break;
+            case 3: {
+                // d sqrt(2/S)/dS = -sqrt(2/S)/(2S), d sqrt(2S)/dS = sqrt(2S)/(2S)
+                const double dD = -D0 / (sm1 * sm1), ts = 0.5 / Sl;
+                c.DR.d[t] = (S)dD; c.DA.d[t] = (S)dD;
+                c.aA.d[t] = (S)(-al * rs * log2e * ts); c.aR.d[t] = (S)(al * rl * log2e * ts);
+                c.hmu.d[t] = (S)(-0.5 * al * rs * ts); c.hlambda.d[t] = (S)(0.5 * al * rl * ts);
+                break;
+            }
+            case 4: c.gam.d[t] = S(1); c.K.d[t] = (S)(cc * cc / (d * d)); c.Kd2.d[t] = (S)(cc * cc); break;
+            // d/dn (-1/(2n)) = 1/(2n^2)
+            case 5: c.n.d[t] = S(1); c.ninv2n.d[t] = (S)(0.5 / (n * n)); break;
+            case 6: c.K.d[t] = (S)(2.0 * gam * cc / (d * d)); c.Kd2.d[t] = (S)(2.0 * gam * cc); break;
+            case 7: c.K.d[t] = (S)(-2.0 * gam * cc * cc / (d * d * d)); c.d2.d[t] = (S)(2.0 * d); break;
+            case 8: c.h.d[t] = S(1); break;
+        }
+    }
+    c.valid = p[P_VALID];
+}
+
 // Angular function and half its derivative for t = cos(theta) - h:
 // minimal g = t^2, g'/2 = t; Tersoff g^T = gam + K t^2 / (d^2 + t^2),
 // g'/2 = K d^2 t / (d^2 + t^2)^2 (Sec. II.A Eq. 8, written without the

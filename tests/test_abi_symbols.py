@@ -20,7 +20,7 @@ def declared_functions():
 
 def test_header_declares_the_three_entry_points():
     names = declared_functions()
-    for n in ("tersoff_eval", "fitness_eval", "fitness_grad", "tersoff_eval_tf", "fitness_eval_tf",
+    for n in ("tersoff_eval", "fitness_eval", "fitness_grad", "tersoff_eval_tf", "fitness_eval_tf", "fitness_grad_tf",
               "mt_set_create",
               "mt_set_attach_reference", "mt_set_destroy", "mt_last_error", "mt_autotune"):
         assert n in names

@@ -3,7 +3,7 @@ Tersoff's angular function, Eq. 8, and Eqs. 11-14 at a free slope S) against
 the oracle, through tersoff_eval_tf and fitness_eval_tf.
 
 Structures: strained 64-atom diamond cells, random packings with coordination
-up to 12 (the one-bond-at-a-time backward sweep above 8 neighbours), small
+up to 9 (the one-bond-at-a-time backward sweep above 8 neighbours), small
 clusters (dimer, trimers, isolated atom) and a 600-atom packing (two-pass
 path).  Parameters: uniform inside the nine-parameter box.  Tolerances as in
 test_gpu_parity: float64 1e-10 relative to the quantity's scale; float32
@@ -165,9 +165,56 @@ def test_out_of_domain_candidates_are_nan_and_isolated(api, precision):
     ts.close()
 
 
-def test_gradient_is_for_the_minimal_potential_only(api):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_tersoff_form_gradient_matches_oracle(api, precision):
+    """dZ/dx over the nine parameters (fitness_grad_tf) against the oracle's
+    autograd, on small cells and packings with coordination up to 9."""
     s = mixed_set(with_large=False)
+    hidden = W.draw_params_full(rng(73), 1)[0]
+    refs = T.reference_data(s, hidden, R1, R2)
     ts = api.from_structures(s)
-    with pytest.raises(ValueError):
-        ts.fitness_grad(W.draw_params_full(rng(72), 2))
+    assert ts.stats()["max_coordination"] <= 12
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    X = W.draw_params_full(rng(74), 4)
+    weights = (1.0, 0.7, 1.3)
+    Z, G = ts.fitness_grad(X, weights, precision=precision)
+    Z, G = Z.cpu().numpy(), G.cpu().numpy()
+    assert G.shape == (4, 9)
+    Zo, Go = T.fitness_grad(s, X, refs, weights, topology=T.topology(s, R2))
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    for c in range(4):
+        print("candidate", c, precision, "max |dZ/dx|", np.abs(Go[c]).max(), flush=True)
+        assert np.abs(G[c] - Go[c]).max() <= tol * np.abs(Go[c]).max()
+        assert abs(Z[c, 0] - Zo[c, 0]) <= (1e-10 if precision == "fp64" else 1e-5) * abs(Zo[c, 0])
+    ts.close()
+
+
+def test_tersoff_form_gradient_matches_central_differences_and_autograd(api):
+    """On the 18-structure uneven subset (every kind at its size extremes):
+    float64 dZ/dx against central differences of the float64 fitness
+    (h = 1e-6), and the same gradient through torch.autograd."""
+    import torch
+    from test_gpu_workloads import sample_structures
+    wl = W.config4()
+    sub = wl.structs.subset(sample_structures(wl.structs))
+    hidden = W.draw_params_full(rng(75), 1)[0]
+    refs = T.reference_data(sub, hidden, R1, R2)
+    ts = api.from_structures(sub)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    X = W.draw_params_full(rng(76), 3)
+    _, G = ts.fitness_grad(X, precision="fp64")
+    G = G.cpu().numpy()
+    h = 1e-6
+    fd = np.zeros_like(G)
+    for k in range(9):
+        Xp, Xm = X.copy(), X.copy()
+        Xp[:, k] += h
+        Xm[:, k] -= h
+        fd[:, k] = (ts.fitness(Xp, precision="fp64").cpu().numpy()[:, 0]
+                    - ts.fitness(Xm, precision="fp64").cpu().numpy()[:, 0]) / (2 * h)
+    for c in range(3):
+        assert np.abs(G[c] - fd[c]).max() <= 1e-5 * np.abs(fd[c]).max()
+    xt = torch.as_tensor(X, device="cuda").requires_grad_(True)
+    api.tersoff_fitness(xt, ts, precision="fp64").sum().backward()
+    assert np.array_equal(xt.grad.cpu().numpy(), G)
     ts.close()

@@ -258,6 +258,12 @@ def tersoff_form_batch(args, api, torch, W, dev):
            "seeds": wl.seeds}
     log(f"Tersoff form batched: {out['ms_per_step']:.4f} ms/generation, {out['value']:.4e} "
         f"atom*cand/s, kernel {kernel_ms:.4f} ms")
+    if args.grad_steps > 0:
+        tg = time_grad(torch, ts, X, args.grad_steps)
+        out["fitness_grad"] = {"value": P * s.n_atoms * args.grad_steps / tg.seconds,
+                               "unit": "atom·candidate fitness-grad evals/s (9 parameters)",
+                               "ms_per_step": tg.seconds / args.grad_steps * 1e3}
+        log(f"Tersoff form fitness_grad: {out['fitness_grad']['ms_per_step']:.3f} ms/generation")
     ts.close()
     return out
 

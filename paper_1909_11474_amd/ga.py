@@ -29,6 +29,11 @@ import numpy as np
 # optimised values of Table 2 and keep every parameter of order unity.
 DEFAULT_LO = (2.0, 1.0, 2.0, 0.1, 0.5, -1.0)
 DEFAULT_HI = (5.0, 2.0, 2.6, 1.0, 1.5, 0.0)
+# Limits for the nine-parameter Tersoff form [D0, alpha, r0, S, gamma, n, c, d, h]
+# (fitness_eval_tf): the minimal box for the shared parameters, S in [1.5, 3],
+# gamma in [0.05, 1], c and d in [0.5, 3].
+TERSOFF_FORM_LO = (2.0, 1.0, 2.0, 1.5, 0.05, 0.5, 0.5, 0.5, -1.0)
+TERSOFF_FORM_HI = (5.0, 2.0, 2.6, 3.0, 1.0, 1.5, 3.0, 3.0, 0.0)
 
 
 @dataclass
@@ -47,7 +52,7 @@ class GAConfig:
 
 
 def decode(genes: np.ndarray, lo: Sequence[float], hi: Sequence[float]) -> np.ndarray:
-    """Genotype [P, 6] in [0, 1] -> phenotype x = lo + g (hi - lo)."""
+    """Genotype [P, n] in [0, 1] -> phenotype x = lo + g (hi - lo), n = len(lo)."""
     lo = np.asarray(lo, dtype=np.float64)
     hi = np.asarray(hi, dtype=np.float64)
     return lo + np.asarray(genes, dtype=np.float64) * (hi - lo)
@@ -60,7 +65,8 @@ def sort_order(z: np.ndarray) -> np.ndarray:
 
 
 class GA:
-    """fitness(x [P,6] float64) -> Z [P]; grad(x [P,6]) -> (Z [P], dZ/dx [P,6]) for refinement."""
+    """fitness(x [P,n] float64) -> Z [P]; grad(x [P,n]) -> (Z [P], dZ/dx [P,n]) for refinement;
+    n = len(cfg.lo) genes (6 for the minimal potential, 9 for the Tersoff form)."""
 
     def __init__(self, cfg: GAConfig, fitness: Callable[[np.ndarray], np.ndarray],
                  grad: Optional[Callable[[np.ndarray], tuple]] = None):
@@ -70,11 +76,14 @@ class GA:
             raise ValueError("crossover needs at least two parents")
         if cfg.refine_top and grad is None:
             raise ValueError("gradient refinement needs a gradient function")
+        if len(cfg.lo) != len(cfg.hi):
+            raise ValueError("lo and hi must have the same length")
+        self.nx = len(cfg.lo)
         self.cfg = cfg
         self.fitness = fitness
         self.grad = grad
         self.rng = np.random.Generator(np.random.PCG64(cfg.seed))
-        self.genes = self.rng.uniform(0.0, 1.0, size=(cfg.pop, 6))
+        self.genes = self.rng.uniform(0.0, 1.0, size=(cfg.pop, self.nx))
         self.z = np.full(cfg.pop, np.nan)
         self.generation = 0
         self.step_size = np.full(cfg.pop, cfg.refine_step0)
@@ -131,13 +140,13 @@ class GA:
             pa = self.rng.integers(0, cfg.n_par, size=n_child)
             pb = self.rng.integers(0, cfg.n_par - 1, size=n_child)
             pb = pb + (pb >= pa)                            # a distinct second parent
-            mask = self.rng.uniform(size=(n_child, 6)) < 0.5
+            mask = self.rng.uniform(size=(n_child, self.nx)) < 0.5
             self.genes[cfg.n_par:] = np.where(mask, self.genes[pa], self.genes[pb])
             self.step_size[cfg.n_par:] = cfg.refine_step0
         # mutation of every non-elite individual
         pm = cfg.mutation0 * (1.0 - self.generation / cfg.n_gen)
-        mut = self.rng.uniform(size=(cfg.pop - 1, 6)) < pm
-        fresh = self.rng.uniform(size=(cfg.pop - 1, 6))
+        mut = self.rng.uniform(size=(cfg.pop - 1, self.nx)) < pm
+        fresh = self.rng.uniform(size=(cfg.pop - 1, self.nx))
         self.genes[1:] = np.where(mut, fresh, self.genes[1:])
         self.generation += 1
         record["seconds"] = time.perf_counter() - t0

@@ -86,3 +86,28 @@ def test_mutation_rate_falls_to_zero():
     before = ga.genes.copy()
     ga.step()
     assert np.array_equal(np.sort(before, axis=0), np.sort(ga.genes, axis=0))
+
+
+def test_tersoff_form_limits_and_nine_gene_run():
+    """The nine-parameter box matches the workload's, and the driver evolves
+    nine genes (the Tersoff form) with refinement, monotone and converging."""
+    assert tuple(G.TERSOFF_FORM_LO) == W.FULL_LO and tuple(G.TERSOFF_FORM_HI) == W.FULL_HI
+    lo, hi = np.asarray(G.TERSOFF_FORM_LO), np.asarray(G.TERSOFF_FORM_HI)
+    target = lo + 0.37 * (hi - lo)
+
+    def f(x):
+        return (((np.asarray(x) - target) / (hi - lo)) ** 2).sum(axis=1)
+
+    def fg(x):
+        x = np.asarray(x)
+        return f(x), 2 * (x - target) / (hi - lo) ** 2
+
+    cfg = G.GAConfig(pop=60, n_par=30, n_gen=80, seed=7, lo=G.TERSOFF_FORM_LO,
+                     hi=G.TERSOFF_FORM_HI, refine_top=4)
+    ga = G.GA(cfg, f, fg)
+    assert ga.genes.shape == (60, 9)
+    bests = [ga.step()["best"] for _ in range(cfg.n_gen)]
+    assert all(b1 <= b0 for b0, b1 in zip(bests, bests[1:]))
+    assert bests[-1] < 1e-4
+    with pytest.raises(ValueError):
+        G.GA(G.GAConfig(lo=G.TERSOFF_FORM_LO), f)

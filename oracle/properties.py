@@ -16,8 +16,8 @@ infrastructure only: imported by tests/ and nothing in the product path).
   and the frequencies sqrt(eig D) / (2 pi).
 
 Each step calls oracle.tersoff.evaluate (float64 autograd) on explicit
-structures; the only shortcuts are a bounded 1-D minimisation and scipy's BFGS
-for the internal relaxation.
+structures; the only shortcuts are a bounded 1-D minimisation and scipy's
+root finder for the internal relaxation.
 """
 from __future__ import annotations
 
@@ -29,7 +29,9 @@ from . import tersoff as T
 
 EV_A3_TO_GPA = 160.21766208          # 1 eV / A^3 in GPa
 M_SI_AMU = 28.0855                   # silicon atomic mass (u)
-THZ_PER_SQRT_EV_A2_AMU = 15.633302   # sqrt(eV / (A^2 u)) / (2 pi) in THz
+# sqrt(eV / (A^2 u)) / (2 pi) in THz, from the CODATA 2018 elementary charge and
+# atomic mass constant
+THZ_PER_SQRT_EV_A2_AMU = math.sqrt(1.602176634e-19 / (1e-20 * 1.66053906660e-27)) / (2 * math.pi) / 1e12
 
 _FCC = np.array([[0.0, 0.0, 0.0], [0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0]])
 
@@ -69,16 +71,21 @@ def stress_gpa(pos, cell, x, R1=2.8, R2=3.2):
     return -Wt / abs(np.linalg.det(cell)) * EV_A3_TO_GPA, out
 
 
-def relax_positions(pos, cell, x, R1=2.8, R2=3.2, gtol=1e-11):
-    """Internal coordinates at fixed cell: BFGS on the energy with the oracle's forces."""
-    from scipy.optimize import minimize
+def relax_positions(pos, cell, x, R1=2.8, R2=3.2, xtol=1e-14):
+    """Internal coordinates at fixed cell: the zero of the oracle's forces on
+    atoms 1.., atom 0 held fixed (removes the rigid translation; the force on
+    atom 0 then vanishes by the sum rule), by MINPACK's hybrid Powell method.
+    Solving F = 0 rather than minimising E reaches the forces' round-off level;
+    a minimiser stalls where energy differences fall below the energy's
+    round-off (about 1e-7 eV/A here)."""
+    from scipy.optimize import root
 
-    def fun(flat):
-        out = T.evaluate(flat.reshape(-1, 3), cell, x, R1, R2)
-        return float(out["E"][0]), -out["F"].ravel()
+    def forces(flat):
+        p = np.vstack([pos[:1], flat.reshape(-1, 3)])
+        return T.evaluate(p, cell, x, R1, R2)["F"][1:].ravel()
 
-    res = minimize(fun, pos.ravel(), jac=True, method="BFGS", options={"gtol": gtol})
-    return res.x.reshape(-1, 3)
+    res = root(forces, pos[1:].ravel(), method="hybr", options={"xtol": xtol})
+    return np.vstack([pos[:1], res.x.reshape(-1, 3)])
 
 
 def elastic_constants(x, a0: float, R1=2.8, R2=3.2, strain=1e-4, shear=1e-3) -> dict:

@@ -66,6 +66,8 @@ def parse():
                     help="GA generations with gradient refinement over the uneven set (0: skip)")
     ap.add_argument("--tf-steps", type=int, default=50,
                     help="generations of the Tersoff-form (9-parameter) GA batch (0: skip)")
+    ap.add_argument("--no-properties", action="store_true",
+                    help="skip timing the 0 K property layer (lattice constant, elastic constants, phonons)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-time budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -268,6 +270,35 @@ def tersoff_form_batch(args, api, torch, W, dev):
     return out
 
 
+def zero_kelvin_properties(torch, W):
+    """Wall time of the 0 K property layer for the Table 2 parameters: lattice
+    constant (two batched grids of 8-atom cells), elastic constants (strained
+    cells and Newton steps of the internal shift), force constants (12 displaced
+    216-atom supercells in one call) and a 200-point dispersion."""
+    import numpy as np
+    from paper_1909_11474_amd import properties as PR
+    x = np.array(W.TABLE2_X)
+    PR.lattice_constant(x)                                  # warm-up
+    t = {}
+    t0 = time.perf_counter()
+    a0, e0 = PR.lattice_constant(x)
+    t["lattice_constant_ms"] = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    ec = PR.elastic_constants(x, a0)
+    t["elastic_constants_ms"] = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    phi, pos, cell = PR.force_constants(x, a0, n=3)
+    q, _ = PR.dispersion_path(a0, per_segment=40)
+    f = PR.frequencies(phi, pos, cell, q)
+    t["phonons_ms"] = (time.perf_counter() - t0) * 1e3
+    out = {"workload": "0 K properties of diamond Si, Table 2 parameters", **t,
+           "a0_A": a0, "E_per_atom_eV": e0, "C11_GPa": ec["C11"], "C12_GPa": ec["C12"],
+           "C44_GPa": ec["C44"], "optical_gamma_THz": float(f[0, 3])}
+    log(f"0 K properties: a0 {a0:.6f} A, C11/C12/C44 {ec['C11']:.2f}/{ec['C12']:.2f}/{ec['C44']:.2f} GPa "
+        f"in {t['lattice_constant_ms']:.1f} + {t['elastic_constants_ms']:.1f} + {t['phonons_ms']:.1f} ms")
+    return out
+
+
 def force_call(args, api, torch, W, dev):
     wl = W.config5()
     s = wl.structs
@@ -387,6 +418,8 @@ def main():
         workloads["ga_refined"] = ga_generations(args, api, torch, W, dev)
     if args.tf_steps > 0:
         workloads["tersoff_form"] = tersoff_form_batch(args, api, torch, W, dev)
+    if not args.no_properties:
+        workloads["properties_0K"] = zero_kelvin_properties(torch, W)
 
     line = {
         "metric": "atom·candidate Tersoff force evals/s and fitness-grad evals/s, batched vs plain",

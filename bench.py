@@ -35,6 +35,34 @@ TUNED_SHAPES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1
                             "tuned_shapes.txt")
 
 
+# HBM traffic of the dominant kernel from two rocprofv3 --pmc passes (FETCH_SIZE,
+# WRITE_SIZE; KiB per dispatch) scaled by what the same counters read for a
+# 256 MiB device-to-device copy (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00), recorded
+# in profiles/k_batched_fit32_ga_batch_traffic.md.  Valid only for the kernel
+# sources it was measured on: reported when their hash still matches.
+PMC_TRAFFIC = {
+    "sources": ["paper_1909_11474_amd/csrc/mt_common.h", "paper_1909_11474_amd/csrc/mt_site.h",
+                "paper_1909_11474_amd/csrc/mt_kernels.h", "paper_1909_11474_amd/csrc/mt_k_fit32.hip"],
+    "sha256_16": "1c1ba57b678942e9",
+    "fetch_bytes": 2466.0 * 1024 * 2.00,
+    "write_bytes": 4250.0 * 1024 * 1.00,
+}
+
+
+def measured_traffic():
+    """Bytes per launch of the dominant kernel from the counter passes, or None
+    if its sources changed since they were taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in PMC_TRAFFIC["sources"]:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != PMC_TRAFFIC["sha256_16"]:
+        return None
+    return PMC_TRAFFIC["fetch_bytes"] + PMC_TRAFFIC["write_bytes"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -66,6 +94,9 @@ def parse():
                     help="GA generations with gradient refinement over the uneven set (0: skip)")
     ap.add_argument("--tf-steps", type=int, default=50,
                     help="generations of the Tersoff-form (9-parameter) GA batch (0: skip)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run three device-to-device copies of this many MiB after the headline "
+                         "(the reference kernel that scales FETCH_SIZE/WRITE_SIZE counters to bytes)")
     ap.add_argument("--no-properties", action="store_true",
                     help="skip timing the 0 K property layer (lattice constant, elastic constants, phonons)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -384,6 +415,16 @@ def main():
                 "ms_per_step": tg.seconds / args.grad_steps * 1e3, "steps": args.grad_steps}
         log(f"fitness_grad: {grad['ms_per_step']:.3f} ms/generation, {grad['value']:.4e} atom*cand/s")
 
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 x {args.copy_probe_mib} MiB device-to-device")
+        del src, dst
+
     # ---- CPU oracle on a bounded sample --------------------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -439,7 +480,8 @@ def main():
                    "precision": "f32 arithmetic, f64 accumulation", "schedule": "batched",
                    "parallelism": "single GPU", "seeds": wl.seeds},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": None},
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS,
+                     "traffic": measured_traffic()},
         "kernel": {"name": "k_batched<float, fit, M<=4>", "avg_ms": kernel_ms, "launches": prof[1],
                    "flop_per_launch": flop_launch, "transcendentals_per_launch": trans_cand * P},
         "host_enqueue_ms_per_step": t.enqueue / args.steps * 1e3,

@@ -94,6 +94,8 @@ def parse():
                     help="GA generations with gradient refinement over the uneven set (0: skip)")
     ap.add_argument("--tf-steps", type=int, default=50,
                     help="generations of the Tersoff-form (9-parameter) GA batch (0: skip)")
+    ap.add_argument("--md-run-steps", type=int, default=200,
+                    help="HNEMD steps of an 8,000-atom diamond cell at 300 K (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run three device-to-device copies of this many MiB after the headline "
                          "(the reference kernel that scales FETCH_SIZE/WRITE_SIZE counters to bytes)")
@@ -330,6 +332,39 @@ def zero_kelvin_properties(torch, W):
     return out
 
 
+def md_run(args, torch, W):
+    """HNEMD of an 8,000-atom diamond cell (10 x 10 x 10 conventional cells,
+    natural isotope masses, 300 K velocities, F_e = 1e-4 /A along z, 1 fs):
+    velocity-Verlet steps per second, each with a position update (neighbour
+    lists and geometry rebuilt), a float64 force call with per-atom virial and
+    heat current, two kicks with the driving force and the kinetic sums."""
+    import numpy as np
+    from paper_1909_11474_amd import md as MDm
+    g = np.random.Generator(np.random.PCG64(21))
+    pos, cell = W.diamond(10, 10, 10)
+    pos = W.displace(g, pos, 0.05)
+    m = MDm.isotope_masses(pos.shape[0], g)
+    v = g.normal(0.0, 1.0, size=pos.shape) * np.sqrt(W.KB_EV * 300.0 / (m[:, None] * W.AMU_A2_FS2_EV))
+    v -= (m[:, None] * v).sum(0) / m.sum()
+    md = MDm.MD(pos, cell, np.array(W.TABLE2_X), m, v, dt=1.0, fe=(0.0, 0.0, 1e-4))
+    md.run(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rec = md.run(args.md_run_steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    e = np.array([r["etot"] for r in rec])
+    out = {"workload": "HNEMD, 8,000-atom diamond Si cell, 300 K, F_e = 1e-4 /A, dt = 1 fs",
+           "steps": args.md_run_steps, "steps_per_s": args.md_run_steps / dt,
+           "ms_per_step": dt / args.md_run_steps * 1e3,
+           "atom_steps_per_s": md.N * args.md_run_steps / dt,
+           "T_mean_K": float(np.mean([r["T"] for r in rec])),
+           "etot_drift_eV_per_atom": float((e[-1] - e[0]) / md.N)}
+    log(f"MD (HNEMD) 8000 atoms: {out['ms_per_step']:.3f} ms/step, {out['atom_steps_per_s']:.3e} atom*steps/s")
+    md.close()
+    return out
+
+
 def force_call(args, api, torch, W, dev):
     wl = W.config5()
     s = wl.structs
@@ -461,6 +496,8 @@ def main():
         workloads["tersoff_form"] = tersoff_form_batch(args, api, torch, W, dev)
     if not args.no_properties:
         workloads["properties_0K"] = zero_kelvin_properties(torch, W)
+    if args.md_run_steps > 0:
+        workloads["md_hnemd_8000"] = md_run(args, torch, W)
 
     line = {
         "metric": "atom·candidate Tersoff force evals/s and fitness-grad evals/s, batched vs plain",

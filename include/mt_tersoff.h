@@ -140,6 +140,17 @@ int mt_set_destroy(mt_set* set);
 int mt_set_stats(const mt_set* set, int64_t* stats);
 
 /*
+ * New positions for the set's atoms (same structures, cells and atom counts),
+ * for molecular dynamics: neighbour lists and bond geometry are rebuilt in the
+ * set's buffers.  pos is device [3][N_tot] float64 in the caller's atom order.
+ * Work lists and captured graphs are rebuilt on the next call, and attached
+ * reference data is dropped (attach it again before fitness calls).
+ * Synchronises the stream.  Errors as for mt_set_create; after a failed update
+ * every later call on the set returns MT_ESTATE (destroy it).
+ */
+int mt_set_update_positions(mt_set* set, const double* pos, void* stream);
+
+/*
  * Copy the neighbour entries out, in the caller's atom numbering, for checks:
  *   i, j    device int32 [n_bonds]  global atom indices (centre, neighbour)
  *   shift   device int32 [3][n_bonds] lattice-vector multiples n1 n2 n3 of the
@@ -214,6 +225,35 @@ int fitness_grad(mt_set* set, const double* x, int P, const double* w, int preci
  */
 int fitness_grad_tf(mt_set* set, const double* x, int P, const double* w, int precision,
                     double* Z, double* dZdx, void* stream);
+
+/*
+ * Molecular-dynamics steps for the potential's application (Sec. IV.C:
+ * equilibrium and homogeneous non-equilibrium MD of diamond Si).  Velocity
+ * Verlet is kick(dt/2), drift(dt), mt_set_update_positions, tersoff_eval,
+ * kick(dt/2).  Units: A, fs, u, eV; arrays device float64 SoA [3][N] in the
+ * caller's atom order; all calls are asynchronous on `stream`.
+ *
+ * mt_md_kick: v_i += dt_half (F_i + F_ext,i - <F_ext>) / (m_i 103.642691),
+ *   F_ext,i = W_i^T F_e (W_i the per-atom virial of tersoff_eval, [9][N]
+ *   row-major), <F_ext> = W^T F_e / N with W the total virial [6] (xx yy zz
+ *   yz zx xy; symmetric).  The external power sum_i F_ext,i . v_i equals
+ *   F_e . J with the heat current J = sum_i W_i v_i of tersoff_eval, and the
+ *   mean is removed so that the driving force adds no momentum.  fe (host [3],
+ *   in 1/A), atom_virial and virial are all NULL for equilibrium MD, or
+ *   all given.  inv_mass device [N] (1/u).
+ * mt_md_drift: r_i += dt v_i.
+ * mt_md_scale: v_i *= lambda (velocity-rescaling thermostats).
+ * mt_md_kinetic: out (device [4]) = sum_i m_i |v_i|^2 (u A^2/fs^2) and the
+ *   momentum sum_i m_i v_i, in a fixed summation order.
+ * Errors: MT_EINVAL for N <= 0 or a NULL required pointer; MT_EHIP if a
+ * launch fails.
+ */
+int mt_md_kick(int N, double* vel, const double* force, const double* atom_virial,
+               const double* virial, const double* fe, const double* inv_mass, double dt_half,
+               void* stream);
+int mt_md_drift(int N, double* pos, const double* vel, double dt, void* stream);
+int mt_md_scale(int N, double* vel, double lambda, void* stream);
+int mt_md_kinetic(int N, const double* vel, const double* mass, double* out, void* stream);
 
 /*
  * Choose launch shapes (block size, candidate tile, schedule) for this set

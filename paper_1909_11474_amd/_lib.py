@@ -40,6 +40,11 @@ SIGNATURES = {
     "mt_set_destroy": (_i, [_vp]),
     "mt_set_stats": (_i, [_vp, ctypes.POINTER(ctypes.c_int64)]),
     "mt_set_neighbors": (_i, [_vp, _vp, _vp, _vp, _vp]),
+    "mt_set_update_positions": (_i, [_vp, _vp, _vp]),
+    "mt_md_kick": (_i, [_i, _vp, _vp, _vp, _vp, ctypes.POINTER(_d), _vp, _d, _vp]),
+    "mt_md_drift": (_i, [_i, _vp, _vp, _d, _vp]),
+    "mt_md_scale": (_i, [_i, _vp, _d, _vp]),
+    "mt_md_kinetic": (_i, [_i, _vp, _vp, _vp, _vp]),
     "tersoff_eval": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tersoff_eval_tf": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fitness_eval": (_i, [_vp, _vp, _i, ctypes.POINTER(_d), _i, _i, _vp, _vp]),

@@ -120,6 +120,7 @@ static int ensure_workspace(mt_set* set, int P, int nv) {
 
 static int check_common(mt_set* set, const double* x, int P, int precision) {
     if (!set) return fail(MT_EINVAL, "set is NULL");
+    if (!set->usable) return fail(MT_ESTATE, "the set's last position update failed; destroy it");
     if (!x) return fail(MT_EINVAL, "x is NULL");
     if (P <= 0) return fail(MT_EINVAL, "P must be positive");
     if (precision != MT_FP64 && precision != MT_FP32_ACC64)
@@ -177,8 +178,24 @@ int mt_set_attach_reference(mt_set* set, const double* e_ref, const double* w_re
                             const double* f_ref, void* stream) {
     if (!set) return fail(MT_EINVAL, "set is NULL");
     if (!e_ref || !w_ref || !f_ref) return fail(MT_EINVAL, "reference pointers must not be NULL");
+    if (!set->usable) return fail(MT_ESTATE, "the set's last position update failed; destroy it");
     clear_graphs(set);
     return attach_reference(set, e_ref, w_ref, f_ref, (hipStream_t)stream);
+}
+
+int mt_set_update_positions(mt_set* set, const double* pos, void* stream) {
+    if (!set || !pos) return fail(MT_EINVAL, "set and pos must not be NULL");
+    if (!set->usable) return fail(MT_ESTATE, "the set's last position update failed; destroy it");
+    // everything derived from positions is rebuilt in the existing buffers;
+    // work lists and captured graphs depend on the coordination layout, and the
+    // stored reference forces on the atom order, so all three are dropped
+    std::vector<int64_t> off(set->h_off.begin(), set->h_off.end());
+    clear_graphs(set);
+    set->plans.clear();
+    set->has_ref = false;
+    const int rc = build_set(set, off.data(), pos, set->cell.as<double>(), (hipStream_t)stream);
+    if (rc != MT_OK) set->usable = false;
+    return rc;
 }
 
 int mt_set_destroy(mt_set* set) {

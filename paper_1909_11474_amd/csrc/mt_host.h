@@ -114,6 +114,8 @@ struct mt_set {
 
     // references (sorted order)
     bool has_ref = false;
+    // false after a failed mt_set_update_positions: the tables are inconsistent
+    bool usable = true;
     mt::DevBuf eref, wref, fref32, fref64;
     double Q[3] = {0, 0, 0};
 

@@ -488,8 +488,11 @@ int build_set(mt_set* set, const int64_t* atom_offset, const double* pos, const 
 
     HIPCHECK(set->pos.reserve(sizeof(double) * 3 * N));
     HIPCHECK(set->cell.reserve(sizeof(double) * 9 * S));
-    HIPCHECK(hipMemcpyAsync(set->pos.p, pos, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, st));
-    HIPCHECK(hipMemcpyAsync(set->cell.p, cell, sizeof(double) * 9 * S, hipMemcpyDeviceToDevice, st));
+    // a rebuild passes the set's own cell (mt_set_update_positions)
+    if (pos != set->pos.p)
+        HIPCHECK(hipMemcpyAsync(set->pos.p, pos, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, st));
+    if (cell != set->cell.p)
+        HIPCHECK(hipMemcpyAsync(set->cell.p, cell, sizeof(double) * 9 * S, hipMemcpyDeviceToDevice, st));
     HIPCHECK(set->st_off.reserve(sizeof(int) * (S + 1)));
     HIPCHECK(hipMemcpyAsync(set->st_off.p, set->h_off.data(), sizeof(int) * (S + 1),
                             hipMemcpyHostToDevice, st));

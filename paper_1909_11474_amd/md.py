@@ -1,0 +1,161 @@
+"""Molecular dynamics on the GPU evaluation path (the potential's application,
+Sec. IV.C: equilibrium MD and homogeneous non-equilibrium MD of diamond Si).
+
+One structure (a periodic cell) per run.  A step is velocity Verlet:
+  mt_md_kick(dt/2), mt_md_drift(dt), mt_set_update_positions,
+  tersoff_eval (forces, virial, per-atom virial, heat current), mt_md_kick(dt/2),
+then, with a thermostat, a velocity rescaling toward the target temperature
+(Berendsen: lambda^2 = 1 + dt/tau (T0/T - 1)).  With a driving force F_e the
+kicks add F_ext,i = W_i^T F_e minus its mean (HNEMD); the heat current J of
+every step is kept for the thermal-conductivity estimate
+kappa = <J> . F_e / (T V |F_e|^2) (Sec. IV.C).
+
+Every step runs in the library's kernels; the host keeps only per-step
+scalars (potential energy, kinetic sums, J).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import api
+
+KB_EV = 8.617333262e-5           # Boltzmann constant (eV/K)
+MV2_TO_EV = 103.642691           # 1 u A^2 / fs^2 in eV
+
+# natural silicon: 28Si, 29Si, 30Si (mass in u, abundance)
+SI_ISOTOPES = ((27.97692653, 0.9223), (28.97649472, 0.0467), (29.97377022, 0.0310))
+
+
+def isotope_masses(n: int, rng: np.random.Generator) -> np.ndarray:
+    """Masses of n Si atoms drawn with the natural isotope abundances (u)."""
+    m = np.array([v for v, _ in SI_ISOTOPES])
+    p = np.array([a for _, a in SI_ISOTOPES])
+    return m[rng.choice(len(m), size=n, p=p / p.sum())]
+
+
+class MD:
+    """Velocity-Verlet MD of one periodic cell with the Tersoff potential x
+    ([6] minimal or [9] Tersoff form), float64 state on the GPU."""
+
+    def __init__(self, pos, cell, x, masses, velocities, dt: float, R1: float = 2.8, R2: float = 3.2,
+                 precision: str = "fp64", fe: Optional[Sequence[float]] = None,
+                 thermostat: Optional[tuple] = None, max_nbr: int = L.MT_MAX_NBR):
+        pos = np.asarray(pos, dtype=np.float64)
+        self.N = pos.shape[0]
+        self.cell = np.asarray(cell, dtype=np.float64)
+        self.volume = abs(float(np.linalg.det(self.cell)))
+        self.dt = float(dt)
+        self.ts = api.TersoffSet(pos, self.cell[None], [0, self.N], R1, R2, max_nbr)
+        self._lib, self.dev = self.ts._lib, self.ts.device
+        kw = dict(dtype=torch.float64, device=self.dev)
+        x = np.asarray(x, dtype=np.float64)
+        self.x = torch.as_tensor(x[None], **kw).contiguous()
+        self._eval = self._lib.tersoff_eval_tf if x.shape[0] == 9 else self._lib.tersoff_eval
+        self.prec = api._prec(precision)
+        self.pos = torch.as_tensor(pos.T.copy(), **kw).contiguous()           # [3][N]
+        self.vel = torch.as_tensor(np.asarray(velocities, np.float64).T.copy(), **kw).contiguous()
+        m = np.asarray(masses, dtype=np.float64)
+        self.mass = torch.as_tensor(m, **kw)
+        self.inv_mass = torch.as_tensor(1.0 / m, **kw)
+        self.E = torch.empty(1, 1, **kw)
+        self.F = torch.empty(1, 3, self.N, **kw)
+        self.W = torch.empty(1, 1, 6, **kw)
+        self.Wi = torch.empty(1, 9, self.N, **kw)
+        self.J = torch.empty(1, 3, **kw)
+        self.kin = torch.empty(4, **kw)
+        self.fe = None if fe is None else (ctypes.c_double * 3)(*[float(v) for v in fe])
+        self.fe_vec = None if fe is None else np.asarray(fe, dtype=np.float64)
+        self.thermostat = thermostat       # (T0 in K, tau in fs) or None
+        self.step_count = 0
+        self._forces()
+
+    # -- library calls -------------------------------------------------------------
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.dev).cuda_stream)
+
+    def _p(self, t):
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _forces(self):
+        L.check(self._eval(self.ts._handle, self._p(self.x), 1, self.prec, L.MT_BATCHED,
+                           self._p(self.E), self._p(self.F), self._p(self.W), self._p(self.Wi),
+                           self._p(self.vel), self._p(self.J), self._stream()), "tersoff_eval")
+
+    def _kick(self, dt_half):
+        drive = self.fe is not None
+        L.check(self._lib.mt_md_kick(self.N, self._p(self.vel), self._p(self.F),
+                                     self._p(self.Wi) if drive else None,
+                                     self._p(self.W) if drive else None,
+                                     self.fe if drive else None, self._p(self.inv_mass),
+                                     float(dt_half), self._stream()), "mt_md_kick")
+
+    def kinetic(self):
+        """(kinetic energy in eV, total momentum [3] in u A/fs)."""
+        L.check(self._lib.mt_md_kinetic(self.N, self._p(self.vel), self._p(self.mass),
+                                        self._p(self.kin), self._stream()), "mt_md_kinetic")
+        k = self.kin.cpu().numpy()
+        return 0.5 * k[0] * MV2_TO_EV, k[1:].copy()
+
+    def temperature(self, ekin: float) -> float:
+        return 2.0 * ekin / (3.0 * self.N * KB_EV)
+
+    # -- stepping ------------------------------------------------------------------
+    def step(self) -> dict:
+        self._kick(0.5 * self.dt)
+        L.check(self._lib.mt_md_drift(self.N, self._p(self.pos), self._p(self.vel), self.dt,
+                                      self._stream()), "mt_md_drift")
+        L.check(self._lib.mt_set_update_positions(self.ts._handle, self._p(self.pos), self._stream()),
+                "mt_set_update_positions")
+        self._forces()
+        self._kick(0.5 * self.dt)
+        ekin, p = self.kinetic()
+        T = self.temperature(ekin)
+        if self.thermostat is not None:
+            T0, tau = self.thermostat
+            lam = np.sqrt(max(1.0 + self.dt / tau * (T0 / max(T, 1e-12) - 1.0), 0.0))
+            L.check(self._lib.mt_md_scale(self.N, self._p(self.vel), float(lam), self._stream()),
+                    "mt_md_scale")
+            ekin, p = self.kinetic()
+            T = self.temperature(ekin)
+        self.step_count += 1
+        epot = float(self.E[0, 0])
+        return {"step": self.step_count, "epot": epot, "ekin": ekin, "etot": epot + ekin, "T": T,
+                "momentum": p, "J": self.J[0].cpu().numpy().copy()}
+
+    def run(self, n: int, every: int = 1) -> list:
+        out = []
+        for k in range(n):
+            rec = self.step()
+            if (k + 1) % every == 0:
+                out.append(rec)
+        return out
+
+    def positions(self) -> np.ndarray:
+        return self.pos.t().cpu().numpy().copy()
+
+    def velocities(self) -> np.ndarray:
+        return self.vel.t().cpu().numpy().copy()
+
+    def external_power(self) -> float:
+        """sum_i F_ext,i . v_i (eV/fs) of the current state, before the mean is
+        removed; equals F_e . J."""
+        Wi = self.Wi[0].cpu().numpy().reshape(3, 3, self.N)
+        v = self.vel.cpu().numpy()
+        return float(np.einsum("a,abi,bi->", self.fe_vec, Wi, v))
+
+    def close(self):
+        self.ts.close()
+
+
+def kappa_hnemd(J_mean: np.ndarray, fe: Sequence[float], T: float, volume: float) -> float:
+    """Thermal conductivity along F_e from the time-averaged heat current:
+    kappa = <J> . F_e / (T V |F_e|^2), J in eV A/fs, F_e in 1/A, T in K, V in A^3;
+    returned in W/(m K)."""
+    fe = np.asarray(fe, dtype=np.float64)
+    k = float(np.dot(J_mean, fe)) / (T * volume * float(np.dot(fe, fe)))   # eV/(fs A K)
+    return k * 1.602176634e-19 / 1e-15 / 1e-10                              # W/(m K)

@@ -1,0 +1,94 @@
+"""GPU molecular dynamics (paper_1909_11474_amd/md.py: mt_md_kick / drift /
+kinetic / scale and mt_set_update_positions around tersoff_eval) against the
+oracle's velocity Verlet (oracle/md.py), and the invariants of the scheme.
+
+Tolerances (float64): 20 steps of 1 fs on a thermal 64-atom cell, positions
+1e-9 A, velocities 1e-10 A/fs, energies 1e-9 eV (rounding differences grow
+slowly over a short chaotic trajectory); momentum 1e-10 u A/fs.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import md as OM
+
+pytestmark = pytest.mark.gpu
+X = np.array(W.TABLE2_X)
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+@pytest.fixture(scope="module")
+def MDm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_11474_amd import md
+    return md
+
+
+def thermal(n, seed, T=500.0, masses=None):
+    pos, cell = W.diamond(n, n, n)
+    g = rng(seed)
+    pos = W.displace(g, pos, 0.03)
+    m = np.full(pos.shape[0], W.M_SI_AMU) if masses is None else masses
+    v = g.normal(0.0, 1.0, size=pos.shape) * np.sqrt(W.KB_EV * T / (m[:, None] * W.AMU_A2_FS2_EV))
+    v -= (m[:, None] * v).sum(0) / m.sum()
+    return pos, cell, m, v
+
+
+@pytest.mark.parametrize("drive", [False, True])
+def test_trajectory_matches_the_oracle(MDm, drive):
+    pos, cell, m, v = thermal(2, 81, masses=MDm.isotope_masses(64, rng(82)))
+    fe = np.array([0.0, 0.0, 3e-3]) if drive else None
+    md = MDm.MD(pos, cell, X, m, v, dt=1.0, fe=fe)
+    recs = md.run(20)
+    po, vo, ro = OM.velocity_verlet(pos, v, m, cell, X, 1.0, 20, fe=fe)
+    print("max |dr|", np.abs(md.positions() - po).max(), "max |dv|", np.abs(md.velocities() - vo).max(), flush=True)
+    assert np.abs(md.positions() - po).max() <= 1e-9
+    assert np.abs(md.velocities() - vo).max() <= 1e-10
+    for r, o in zip(recs, ro):
+        assert abs(r["epot"] - o["epot"]) <= 1e-9 and abs(r["ekin"] - o["ekin"]) <= 1e-9
+        assert np.abs(r["momentum"]).max() <= 1e-10
+    md.close()
+
+
+def test_heat_current_and_driving_power(MDm):
+    """The kernel's J equals sum_i W_i v_i, and the driving force's power is F_e . J."""
+    pos, cell, m, v = thermal(2, 83)
+    fe = np.array([1e-3, -2e-3, 4e-3])
+    md = MDm.MD(pos, cell, X, m, v, dt=1.0, fe=fe)
+    md.run(5)
+    md._forces()                          # J at the current (full-step) velocities
+    Wi = md.Wi[0].cpu().numpy().reshape(3, 3, md.N)
+    vel = md.vel.cpu().numpy()
+    J = np.einsum("abi,bi->a", Wi, vel)
+    Jk = md.J[0].cpu().numpy()
+    assert np.abs(Jk - J).max() <= 1e-12 * max(np.abs(J).max(), 1.0)
+    assert abs(md.external_power() - fe @ Jk) <= 1e-12 * max(abs(fe @ Jk), 1e-6)
+    md.close()
+
+
+def test_nve_energy_conservation_and_thermostat(MDm):
+    """512 atoms: NVE total energy stays within 2e-4 eV/atom over 200 fs; a
+    Berendsen thermostat brings 100 K to 600 K."""
+    pos, cell, m, v = thermal(4, 84, T=600.0)
+    md = MDm.MD(pos, cell, X, m, v, dt=1.0)
+    e = np.array([r["etot"] for r in md.run(200)])
+    print("NVE spread per atom", np.ptp(e) / md.N, flush=True)
+    assert np.ptp(e) / md.N < 2e-4
+    md.close()
+    pos, cell, m, v = thermal(4, 85, T=100.0)
+    md = MDm.MD(pos, cell, X, m, v, dt=1.0, thermostat=(600.0, 20.0))
+    T = np.array([r["T"] for r in md.run(300)])
+    print("T start", T[0], "end", T[-20:].mean(), flush=True)
+    assert abs(T[-50:].mean() - 600.0) < 60.0
+    md.close()
+
+
+def test_hnemd_estimator_units(MDm):
+    """kappa = <J> . F_e / (T V |F_e|^2) converts eV/(fs A K) to W/(m K)."""
+    k = MDm.kappa_hnemd(np.array([0.0, 0.0, 1.0]), [0.0, 0.0, 1.0], 1.0, 1.0)
+    assert abs(k - 1.602176634e6) < 1e-3

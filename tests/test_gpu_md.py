@@ -92,3 +92,42 @@ def test_hnemd_estimator_units(MDm):
     """kappa = <J> . F_e / (T V |F_e|^2) converts eV/(fs A K) to W/(m K)."""
     k = MDm.kappa_hnemd(np.array([0.0, 0.0, 1.0]), [0.0, 0.0, 1.0], 1.0, 1.0)
     assert abs(k - 1.602176634e6) < 1e-3
+
+
+def test_position_update_semantics(MDm):
+    """Updating to the same positions reproduces the bits; an update drops the
+    reference data (MT_ENOREF until it is attached again); an update that
+    overflows the neighbour capacity leaves the set unusable (MT_ESTATE)."""
+    import torch
+    from paper_1909_11474_amd import api, _lib as L
+    from oracle import tersoff as T
+    wl = W.config2(n_struct=3, pop=4)
+    refs = T.reference_data(wl.structs, wl.hidden_x, 2.8, 3.2)
+    ts = api.from_structures(wl.structs)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    E0 = ts.tersoff_eval(wl.population, precision="fp64")["E"].clone()
+    Z0 = ts.fitness(wl.population, precision="fp64").clone()
+    pos = torch.as_tensor(wl.structs.pos.T.copy(), device="cuda").contiguous()
+    L.check(ts._lib.mt_set_update_positions(ts._handle, ctypes_ptr(pos), None), "update")
+    assert torch.equal(ts.tersoff_eval(wl.population, precision="fp64")["E"], E0)
+    with pytest.raises(L.MTError) as e:
+        ts.fitness(wl.population, precision="fp64")
+    assert e.value.code == L.MT_ENOREF
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    assert torch.equal(ts.fitness(wl.population, precision="fp64"), Z0)
+    ts.close()
+    # capacity 4: a squeezed cell gives atoms more than 4 neighbours
+    pos, cell = W.diamond(1, 1, 1)
+    ts = api.TersoffSet(pos, cell[None], [0, 8], 2.8, 3.2, max_nbr=4)
+    squeezed = torch.as_tensor((pos * 0.8).T.copy(), device="cuda").contiguous()
+    rc = ts._lib.mt_set_update_positions(ts._handle, ctypes_ptr(squeezed), None)
+    assert rc == L.MT_ENBR_OVERFLOW
+    with pytest.raises(L.MTError) as e:
+        ts.tersoff_eval(X[None], precision="fp64")
+    assert e.value.code == L.MT_ESTATE
+    ts.close()
+
+
+def ctypes_ptr(t):
+    import ctypes
+    return ctypes.c_void_p(t.data_ptr())

@@ -151,6 +151,24 @@ int mt_set_stats(const mt_set* set, int64_t* stats);
 int mt_set_update_positions(mt_set* set, const double* pos, void* stream);
 
 /*
+ * Neighbour lists with a Verlet skin: rebuild the set's lists with every pair
+ * closer than R2 + skin (A, >= 0; pairs beyond R2 carry f_C = 0 and add
+ * nothing), so that mt_set_update_geometry can move atoms without a new
+ * search until some atom has moved skin/2 since the last rebuild
+ * (mt_set_update_positions).  mt_set_neighbors then lists the skin pairs too.
+ * Synchronises the stream; errors as for mt_set_update_positions.
+ */
+int mt_set_list_skin(mt_set* set, double skin, void* stream);
+
+/*
+ * New positions with the neighbour lists of the last rebuild: bond geometry
+ * only, asynchronous on `stream`, no host synchronisation.  Correct while no
+ * atom has moved more than skin/2 since that rebuild (the caller checks, for
+ * instance with mt_md_max_disp).  pos device [3][N_tot].
+ */
+int mt_set_update_geometry(mt_set* set, const double* pos, void* stream);
+
+/*
  * Copy the neighbour entries out, in the caller's atom numbering, for checks:
  *   i, j    device int32 [n_bonds]  global atom indices (centre, neighbour)
  *   shift   device int32 [3][n_bonds] lattice-vector multiples n1 n2 n3 of the
@@ -254,6 +272,8 @@ int mt_md_kick(int N, double* vel, const double* force, const double* atom_viria
 int mt_md_drift(int N, double* pos, const double* vel, double dt, void* stream);
 int mt_md_scale(int N, double* vel, double lambda, void* stream);
 int mt_md_kinetic(int N, const double* vel, const double* mass, double* out, void* stream);
+/* out (device [1]) = max_i |r_i - ref_i|^2 (A^2), for the skin check. */
+int mt_md_max_disp(int N, const double* pos, const double* ref, double* out, void* stream);
 
 /*
  * Choose launch shapes (block size, candidate tile, schedule) for this set

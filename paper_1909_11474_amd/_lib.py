@@ -41,6 +41,9 @@ SIGNATURES = {
     "mt_set_stats": (_i, [_vp, ctypes.POINTER(ctypes.c_int64)]),
     "mt_set_neighbors": (_i, [_vp, _vp, _vp, _vp, _vp]),
     "mt_set_update_positions": (_i, [_vp, _vp, _vp]),
+    "mt_set_list_skin": (_i, [_vp, _d, _vp]),
+    "mt_set_update_geometry": (_i, [_vp, _vp, _vp]),
+    "mt_md_max_disp": (_i, [_i, _vp, _vp, _vp, _vp]),
     "mt_md_kick": (_i, [_i, _vp, _vp, _vp, _vp, ctypes.POINTER(_d), _vp, _d, _vp]),
     "mt_md_drift": (_i, [_i, _vp, _vp, _d, _vp]),
     "mt_md_scale": (_i, [_i, _vp, _d, _vp]),

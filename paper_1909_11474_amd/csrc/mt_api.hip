@@ -190,12 +190,34 @@ int mt_set_update_positions(mt_set* set, const double* pos, void* stream) {
     // work lists and captured graphs depend on the coordination layout, and the
     // stored reference forces on the atom order, so all three are dropped
     std::vector<int64_t> off(set->h_off.begin(), set->h_off.end());
-    clear_graphs(set);
-    set->plans.clear();
+    const auto layout = std::make_tuple(set->h_kmax, set->h_xsize, set->h_npad, set->h_large, set->nslots);
     set->has_ref = false;
     const int rc = build_set(set, off.data(), pos, set->cell.as<double>(), (hipStream_t)stream);
-    if (rc != MT_OK) set->usable = false;
-    return rc;
+    if (rc != MT_OK) {
+        set->usable = false;
+        return rc;
+    }
+    // the work lists (and graphs of them) stay valid while every structure keeps
+    // its coordination class, exchange-slot layout and padded size
+    if (layout != std::make_tuple(set->h_kmax, set->h_xsize, set->h_npad, set->h_large, set->nslots)) {
+        clear_graphs(set);
+        set->plans.clear();
+    }
+    return MT_OK;
+}
+
+int mt_set_update_geometry(mt_set* set, const double* pos, void* stream) {
+    if (!set || !pos) return fail(MT_EINVAL, "set and pos must not be NULL");
+    if (!set->usable) return fail(MT_ESTATE, "the set's last position update failed; destroy it");
+    return update_geometry(set, pos, (hipStream_t)stream);
+}
+
+int mt_set_list_skin(mt_set* set, double skin, void* stream) {
+    if (!set) return fail(MT_EINVAL, "set is NULL");
+    if (!set->usable) return fail(MT_ESTATE, "the set's last position update failed; destroy it");
+    if (!(skin >= 0.0) || !std::isfinite(skin)) return fail(MT_EINVAL, "skin must be finite and >= 0");
+    set->skin = skin;
+    return mt_set_update_positions(set, set->pos.as<double>(), stream);
 }
 
 int mt_set_destroy(mt_set* set) {

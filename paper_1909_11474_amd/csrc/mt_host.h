@@ -83,6 +83,13 @@ struct GraphKey {             // what a captured fitness graph depends on
     }
 };
 
+// Temporaries of the neighbour search and table build, kept with the set so
+// that position updates (molecular dynamics) reuse them instead of allocating.
+struct BuildScratch {
+    DevBuf meta, atom_bin, atom_wrap, bin_count, bin_start, bin_fill, bin_atoms, cnt, ent_j, ent_sh,
+        inv, flags, st_nb, st_trip;
+};
+
 struct GraphEntry {
     GraphKey key;
     hipGraph_t graph = nullptr;
@@ -97,6 +104,7 @@ struct mt_set {
     int max_atoms = 0, n_batched = 0, n_large = 0;
     size_t lds_max = 65536;   // dynamic LDS bytes a block may use on the set's device
     double R1 = 0, R2 = 0;
+    double skin = 0;          // neighbour lists hold pairs closer than R2 + skin
     int device = 0;
 
     // host copies of per-structure tables
@@ -130,6 +138,7 @@ struct mt_set {
     mt::DevBuf zwork;                        // [P][4] scratch for fitness_grad
     mt::DevBuf gbuf;                         // large path bond gradients
     mt::DevBuf scalars;                      // small device scratch
+    mt::BuildScratch build;                  // neighbour-search temporaries
 
     std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<mt::ItemPlan>> plans;
     std::map<std::pair<int, int>, mt::LaunchCfg> tuned;     // (P, precision) -> cfg
@@ -153,6 +162,8 @@ int build_set(mt_set* set, const int64_t* atom_offset, const double* pos, const 
 int attach_reference(mt_set* set, const double* e_ref, const double* w_ref, const double* f_ref,
                      hipStream_t stream);
 int export_neighbors(const mt_set* set, int32_t* i, int32_t* j, int32_t* shift, hipStream_t stream);
+// New positions with the neighbour lists of the last build (no host sync).
+int update_geometry(mt_set* set, const double* pos, hipStream_t stream);
 
 // mt_eval.hip
 int launch_batched(mt_set* set, const LaunchCfg& cfg, int P, int precision, int mode,

@@ -86,6 +86,29 @@ __global__ __launch_bounds__(1024) void k_kinetic(int N, const double* __restric
     if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
+// out[0] = max_i |r_i - r0_i|^2 (one block, exact: max is order independent).
+__global__ __launch_bounds__(1024) void k_max_disp(int N, const double* __restrict__ pos,
+                                                   const double* __restrict__ ref,
+                                                   double* __restrict__ out) {
+    __shared__ double sh[1024];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        double d2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double d = pos[(size_t)k * N + i] - ref[(size_t)k * N + i];
+            d2 += d * d;
+        }
+        a = a > d2 ? a : d2;
+    }
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
 }  // namespace
 }  // namespace mt
 
@@ -121,6 +144,13 @@ int mt_md_scale(int N, double* vel, double lambda, void* stream) {
     hipLaunchKernelGGL(k_scale, dim3(blocks_for(N)), dim3(256), 0, (hipStream_t)stream, N, vel, lambda);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? MT_OK : hip_fail(e, "k_scale");
+}
+
+int mt_md_max_disp(int N, const double* pos, const double* ref, double* out, void* stream) {
+    if (N <= 0 || !pos || !ref || !out) { set_error("N must be positive, pointers not NULL"); return MT_EINVAL; }
+    hipLaunchKernelGGL(k_max_disp, dim3(1), dim3(1024), 0, (hipStream_t)stream, N, pos, ref, out);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MT_OK : hip_fail(e, "k_max_disp");
 }
 
 int mt_md_kinetic(int N, const double* vel, const double* mass, double* out, void* stream) {

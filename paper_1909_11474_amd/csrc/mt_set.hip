@@ -497,10 +497,14 @@ int build_set(mt_set* set, const int64_t* atom_offset, const double* pos, const 
     HIPCHECK(hipMemcpyAsync(set->st_off.p, set->h_off.data(), sizeof(int) * (S + 1),
                             hipMemcpyHostToDevice, st));
 
-    DevBuf meta, atom_bin, atom_wrap, bin_count, bin_start, bin_fill, bin_atoms, cnt, ent_j, ent_sh,
-        inv, flags, st_nb, st_trip;
+    BuildScratch& B = set->build;
+    DevBuf &meta = B.meta, &atom_bin = B.atom_bin, &atom_wrap = B.atom_wrap, &bin_count = B.bin_count,
+           &bin_start = B.bin_start, &bin_fill = B.bin_fill, &bin_atoms = B.bin_atoms, &cnt = B.cnt,
+           &ent_j = B.ent_j, &ent_sh = B.ent_sh, &inv = B.inv, &flags = B.flags, &st_nb = B.st_nb,
+           &st_trip = B.st_trip;
     HIPCHECK(meta.reserve(sizeof(StructMeta) * S));
-    k_struct_meta<<<grid_of(S, 128), 128, 0, st>>>(S, set->cell.as<double>(), set->R2,
+    const double rlist = set->R2 + set->skin;
+    k_struct_meta<<<grid_of(S, 128), 128, 0, st>>>(S, set->cell.as<double>(), rlist,
                                                     meta.as<StructMeta>());
     HIPCHECK(hipGetLastError());
     std::vector<StructMeta> hm(S);
@@ -544,7 +548,7 @@ int build_set(mt_set* set, const int64_t* atom_offset, const double* pos, const 
     HIPCHECK(ent_sh.reserve(sizeof(int) * (size_t)kcap * N));
     HIPCHECK(flags.reserve(sizeof(int) * 4));
     HIPCHECK(hipMemsetAsync(flags.p, 0, sizeof(int) * 4, st));
-    k_search<<<grid_of(N, 128), 128, 0, st>>>(N, S, kcap, set->R2, set->st_off.as<int>(),
+    k_search<<<grid_of(N, 128), 128, 0, st>>>(N, S, kcap, rlist, set->st_off.as<int>(),
                                                set->pos.as<double>(), meta.as<StructMeta>(),
                                                atom_bin.as<int>(), atom_wrap.as<int>(),
                                                bin_start.as<int>(), bin_atoms.as<int>(), cnt.as<int>(),
@@ -556,7 +560,8 @@ int build_set(mt_set* set, const int64_t* atom_offset, const double* pos, const 
     if (hflags & 2) { set_error("coincident atoms (distance 0 between an atom and a neighbour image)"); return MT_ECOINCIDENT; }
     if (hflags & 4) { set_error("invalid cell or image shift out of range"); return MT_EINVAL; }
     if (hflags & 1) {
-        set_error("an atom has more than max_nbr = " + std::to_string(kcap) + " neighbours within R2");
+        set_error("an atom has more than max_nbr = " + std::to_string(kcap) +
+                  " neighbours within R2 + skin");
         return MT_ENBR_OVERFLOW;
     }
 
@@ -655,6 +660,23 @@ int build_set(mt_set* set, const int64_t* atom_offset, const double* pos, const 
         set_error("neighbour lists are not symmetric (reverse entry missing)");
         return MT_EINVAL;
     }
+    return MT_OK;
+}
+
+int update_geometry(mt_set* set, const double* pos, hipStream_t st) {
+    const int S = set->S, N = set->N, kcap = set->kcap;
+    BuildScratch& B = set->build;
+    const size_t KN = (size_t)kcap * N;
+    if (pos != set->pos.p)
+        HIPCHECK(hipMemcpyAsync(set->pos.p, pos, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, st));
+    k_geometry<<<grid_of((long long)KN, 256), 256, 0, st>>>(
+        N, S, kcap, set->R1, set->R2, set->st_off.as<int>(), set->pos.as<double>(),
+        B.meta.as<StructMeta>(), set->perm.as<int>(), B.inv.as<int>(), B.cnt.as<int>(), B.ent_j.as<int>(),
+        B.ent_sh.as<int>(), set->lbo.as<int>(), set->xbase.as<int>(), set->st_npad.as<int>(),
+        set->gf.as<float>(), set->gf_rlo.as<float>(), set->gpk.as<float4>(),
+        set->gd.as<double>(), set->rev.as<int>(), set->revc.as<int>(), set->jl.as<int>(), set->nbr_j.as<int>(),
+        set->nbr_sh.as<int>(), B.flags.as<int>());
+    HIPCHECK(hipGetLastError());
     return MT_OK;
 }
 

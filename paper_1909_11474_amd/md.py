@@ -2,13 +2,18 @@
 Sec. IV.C: equilibrium MD and homogeneous non-equilibrium MD of diamond Si).
 
 One structure (a periodic cell) per run.  A step is velocity Verlet:
-  mt_md_kick(dt/2), mt_md_drift(dt), mt_set_update_positions,
+  mt_md_kick(dt/2), mt_md_drift(dt), position update,
   tersoff_eval (forces, virial, per-atom virial, heat current), mt_md_kick(dt/2),
 then, with a thermostat, a velocity rescaling toward the target temperature
 (Berendsen: lambda^2 = 1 + dt/tau (T0/T - 1)).  With a driving force F_e the
 kicks add F_ext,i = W_i^T F_e minus its mean (HNEMD); the heat current J of
 every step is kept for the thermal-conductivity estimate
 kappa = <J> . F_e / (T V |F_e|^2) (Sec. IV.C).
+
+The position update rebuilds the neighbour lists (mt_set_update_positions)
+when skin = 0; with a Verlet skin the lists hold pairs within R2 + skin and
+only the bond geometry is recomputed (mt_set_update_geometry) until some atom
+has moved skin/2 since the last rebuild (mt_md_max_disp).
 
 Every step runs in the library's kernels; the host keeps only per-step
 scalars (potential energy, kinetic sums, J).
@@ -44,7 +49,8 @@ class MD:
 
     def __init__(self, pos, cell, x, masses, velocities, dt: float, R1: float = 2.8, R2: float = 3.2,
                  precision: str = "fp64", fe: Optional[Sequence[float]] = None,
-                 thermostat: Optional[tuple] = None, max_nbr: int = L.MT_MAX_NBR):
+                 thermostat: Optional[tuple] = None, max_nbr: int = L.MT_MAX_NBR,
+                 skin: float = 0.0):
         pos = np.asarray(pos, dtype=np.float64)
         self.N = pos.shape[0]
         self.cell = np.asarray(cell, dtype=np.float64)
@@ -72,6 +78,12 @@ class MD:
         self.fe_vec = None if fe is None else np.asarray(fe, dtype=np.float64)
         self.thermostat = thermostat       # (T0 in K, tau in fs) or None
         self.step_count = 0
+        self.skin = float(skin)
+        self.rebuilds = 0
+        if self.skin > 0:
+            L.check(self._lib.mt_set_list_skin(self.ts._handle, self.skin, self._stream()), "mt_set_list_skin")
+            self.ref = self.pos.clone()
+            self.disp = torch.empty(1, **kw)
         self._forces()
 
     # -- library calls -------------------------------------------------------------
@@ -94,6 +106,19 @@ class MD:
                                      self.fe if drive else None, self._p(self.inv_mass),
                                      float(dt_half), self._stream()), "mt_md_kick")
 
+    def _update_positions(self):
+        if self.skin > 0:
+            L.check(self._lib.mt_md_max_disp(self.N, self._p(self.pos), self._p(self.ref),
+                                             self._p(self.disp), self._stream()), "mt_md_max_disp")
+            if float(self.disp[0]) < (0.5 * self.skin) ** 2:
+                L.check(self._lib.mt_set_update_geometry(self.ts._handle, self._p(self.pos),
+                                                         self._stream()), "mt_set_update_geometry")
+                return
+            self.ref.copy_(self.pos)
+        L.check(self._lib.mt_set_update_positions(self.ts._handle, self._p(self.pos), self._stream()),
+                "mt_set_update_positions")
+        self.rebuilds += 1
+
     def kinetic(self):
         """(kinetic energy in eV, total momentum [3] in u A/fs)."""
         L.check(self._lib.mt_md_kinetic(self.N, self._p(self.vel), self._p(self.mass),
@@ -109,8 +134,7 @@ class MD:
         self._kick(0.5 * self.dt)
         L.check(self._lib.mt_md_drift(self.N, self._p(self.pos), self._p(self.vel), self.dt,
                                       self._stream()), "mt_md_drift")
-        L.check(self._lib.mt_set_update_positions(self.ts._handle, self._p(self.pos), self._stream()),
-                "mt_set_update_positions")
+        self._update_positions()
         self._forces()
         self._kick(0.5 * self.dt)
         ekin, p = self.kinetic()

@@ -8,6 +8,10 @@ fitness (Sec. III.B of the paper).  The neighbour lists and bond geometry are
 built once per structure set (the cutoffs are fixed, not fitted) and are not
 part of a step.
 
+Before the W untimed warm-up steps the fitness workloads (headline, uneven,
+Tersoff form) run for 0.25 s, so that the GPU has left its idle clock; the
+timed region then holds exactly K steps.
+
 Headline workload: 200 candidates x 100 strained 64-atom diamond Si cells,
 float32 arithmetic with float64 accumulation; reference data from a hidden
 parameter set evaluated by the library's float64 path.  The same run also
@@ -80,7 +84,7 @@ def flops_per_atom(M: np.ndarray) -> np.ndarray:
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--grad-steps", type=int, default=10)
@@ -152,10 +156,22 @@ def set_flops(ts, n_atoms):
     return float(flops_per_atom(M).sum()), float(6 * M.sum())
 
 
+def spin_up(torch, call, seconds=0.25):
+    """Run `call` untimed for `seconds` so that the GPU leaves its idle clock
+    before the warm-up steps: a few milliseconds of work (the default warm-up)
+    leave the clock ramping, and a generation measured then takes ~7 % longer."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(50):
+            call()
+        torch.cuda.synchronize()
+
+
 def time_generations(torch, ts, X, Z, steps, warmup):
     """GPU time of `steps` back-to-back fitness_eval calls (graph replay or direct,
     as tuned), then the batched kernels' own time from events around each launch."""
     call = ts.fitness_call(X, Z, precision="fp32", schedule="batched")
+    spin_up(torch, call)
     for _ in range(warmup):
         call()
     with Timer(torch) as t:

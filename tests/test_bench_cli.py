@@ -1,0 +1,44 @@
+"""bench.py's host-side contract, on the CPU: more than one GPU is refused
+with a JSON message, the algorithmic flop count per atom follows its stated
+formula, and the recorded HBM traffic is reported only for the kernel sources
+it was measured on."""
+import importlib.util
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def load_bench():
+    spec = importlib.util.spec_from_file_location("bench_module", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
+
+
+def test_flops_per_atom_formula():
+    b = load_bench()
+    # diamond (M = 4): 6 bond pairs x 31 + 4 bonds x 70 + 9
+    assert b.flops_per_atom(np.array([4]))[0] == 6 * 31 + 4 * 70 + 9 == 475
+    assert b.flops_per_atom(np.array([0]))[0] == 9
+    assert b.flops_per_atom(np.array([12]))[0] == 66 * 31 + 12 * 70 + 9
+
+
+def test_traffic_is_tied_to_the_measured_sources(tmp_path):
+    b = load_bench()
+    t = b.measured_traffic()
+    assert t is None or abs(t - (b.PMC_TRAFFIC["fetch_bytes"] + b.PMC_TRAFFIC["write_bytes"])) < 1
+    b.PMC_TRAFFIC = dict(b.PMC_TRAFFIC, sha256_16="0" * 16)
+    assert b.measured_traffic() is None

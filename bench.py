@@ -72,11 +72,21 @@ def log(*a):
 
 
 def flops_per_atom(M: np.ndarray) -> np.ndarray:
-    """Algorithmic flops of one atom for one candidate in the batched kernel's
-    formulation (FMA = 2, each transcendental = 1): 31 per unordered bond pair
-    (zeta forward 6, gradient backward 25), 70 per bond (pair terms, bond order
-    with 6 transcendentals, gradient assembly, force exchange, virial) and 9 per
-    atom (site energy, force residual)."""
+    """Algorithmic flops of one atom for one candidate (FMA = 2, transcendentals
+    counted separately): the plain chain-rule formulation of energy, forces and
+    virial, 44 per directed pair (10 forward, 34 backward) and 55 per ordered
+    triplet (5 forward, 50 backward); 836 for a diamond atom (M = 4)."""
+    M = np.asarray(M, dtype=np.int64)
+    return 44 * M + 55 * M * (M - 1)
+
+
+def kernel_flops_per_atom(M: np.ndarray) -> np.ndarray:
+    """Flops the batched kernel's own formulation issues per atom and candidate
+    (FMA = 2, each transcendental = 1): 31 per unordered bond pair (zeta
+    forward 6, gradient backward 25: cos(theta) once per pair, the radial part
+    through u_j . V_j), 70 per bond (pair terms, bond order with 6
+    transcendentals, gradient assembly, force exchange, virial) and 9 per atom
+    (site energy, force residual); 475 for a diamond atom."""
     M = np.asarray(M, dtype=np.int64)
     return 31 * (M * (M - 1) // 2) + 70 * M + 9
 
@@ -151,9 +161,11 @@ def make_set(api, torch, wl):
 
 
 def set_flops(ts, n_atoms):
+    """(algorithmic flops, transcendentals, kernel-formulation flops) of one
+    candidate over the set, from each atom's coordination."""
     i, _, _ = ts.neighbors()
     M = np.bincount(i, minlength=n_atoms)
-    return float(flops_per_atom(M).sum()), float(6 * M.sum())
+    return float(flops_per_atom(M).sum()), float(6 * M.sum()), float(kernel_flops_per_atom(M).sum())
 
 
 def spin_up(torch, call, seconds=0.25):
@@ -210,7 +222,7 @@ def uneven_batching(args, api, torch, W, dev):
     log(f"workload: {wl.name}; atoms {s.n_atoms}, population {P}")
     ts, _, t_create = make_set(api, torch, wl)
     st = ts.stats()
-    flop_cand, _ = set_flops(ts, s.n_atoms)
+    flop_cand, _, _ = set_flops(ts, s.n_atoms)
     X = torch.as_tensor(wl.population, dtype=torch.float64, device=dev).contiguous()
     Z = torch.empty(P, 4, dtype=torch.float64, device=dev)
     t0 = time.perf_counter()
@@ -429,7 +441,7 @@ def main():
     ts, (e_ref, w_ref, f_ref), t_create = make_set(api, torch, wl)
     st = ts.stats()
     log("set:", st, f"created in {t_create * 1e3:.1f} ms")
-    flop_cand, trans_cand = set_flops(ts, s.n_atoms)
+    flop_cand, trans_cand, kflop_cand = set_flops(ts, s.n_atoms)
     flop_launch = flop_cand * P
 
     X = torch.as_tensor(wl.population, dtype=torch.float64, device=dev).contiguous()
@@ -448,8 +460,9 @@ def main():
         f"(wall {t.wall * 1e3:.3f} ms, host enqueue {t.enqueue * 1e3:.3f} ms for {args.steps} generations)")
     kernel_ms = prof[0] / max(prof[1], 1)
     achieved = flop_launch / (kernel_ms * 1e-3) / 1e12
+    kernel_tflops = kflop_cand * P / (kernel_ms * 1e-3) / 1e12
     log(f"batched kernel: {kernel_ms:.4f} ms/launch over {prof[1]} launches, "
-        f"{achieved:.2f} TFLOP/s algorithmic")
+        f"{achieved:.2f} TFLOP/s algorithmic, {kernel_tflops:.2f} TFLOP/s in the kernel's formulation")
     Zb = Z.clone()
 
     plain = None
@@ -539,7 +552,10 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS,
                      "traffic": measured_traffic()},
         "kernel": {"name": "k_batched<float, fit, M<=4>", "avg_ms": kernel_ms, "launches": prof[1],
-                   "flop_per_launch": flop_launch, "transcendentals_per_launch": trans_cand * P},
+                   "flop_per_launch": flop_launch, "transcendentals_per_launch": trans_cand * P,
+                   "formulation_flop_per_launch": kflop_cand * P,
+                   "formulation_tflops": kernel_tflops,
+                   "formulation_frac": kernel_tflops / FP32_VALU_PEAK_TFLOPS},
         "host_enqueue_ms_per_step": t.enqueue / args.steps * 1e3,
         "plain": plain,
         "fitness_grad": grad,

@@ -30,10 +30,12 @@ def test_more_than_one_gpu_is_refused():
 
 def test_flops_per_atom_formula():
     b = load_bench()
-    # diamond (M = 4): 6 bond pairs x 31 + 4 bonds x 70 + 9
-    assert b.flops_per_atom(np.array([4]))[0] == 6 * 31 + 4 * 70 + 9 == 475
-    assert b.flops_per_atom(np.array([0]))[0] == 9
-    assert b.flops_per_atom(np.array([12]))[0] == 66 * 31 + 12 * 70 + 9
+    # algorithmic: 44 per directed pair + 55 per ordered triplet; diamond 836
+    assert b.flops_per_atom(np.array([4]))[0] == 4 * 44 + 12 * 55 == 836
+    assert b.flops_per_atom(np.array([0]))[0] == 0
+    # the kernel's formulation: 6 bond pairs x 31 + 4 bonds x 70 + 9 for diamond
+    assert b.kernel_flops_per_atom(np.array([4]))[0] == 6 * 31 + 4 * 70 + 9 == 475
+    assert b.kernel_flops_per_atom(np.array([12]))[0] == 66 * 31 + 12 * 70 + 9
 
 
 def test_traffic_is_tied_to_the_measured_sources(tmp_path):

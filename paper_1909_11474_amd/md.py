@@ -137,19 +137,21 @@ class MD:
         self._update_positions()
         self._forces()
         self._kick(0.5 * self.dt)
-        ekin, p = self.kinetic()
+        L.check(self._lib.mt_md_kinetic(self.N, self._p(self.vel), self._p(self.mass),
+                                        self._p(self.kin), self._stream()), "mt_md_kinetic")
+        # one read-back per step: E, J and the kinetic sums together
+        sc = torch.cat([self.E.view(-1), self.J.view(-1), self.kin]).cpu().numpy()
+        epot, J, ekin, p = float(sc[0]), sc[1:4].copy(), 0.5 * sc[4] * MV2_TO_EV, sc[5:8].copy()
         T = self.temperature(ekin)
         if self.thermostat is not None:
             T0, tau = self.thermostat
             lam = np.sqrt(max(1.0 + self.dt / tau * (T0 / max(T, 1e-12) - 1.0), 0.0))
             L.check(self._lib.mt_md_scale(self.N, self._p(self.vel), float(lam), self._stream()),
                     "mt_md_scale")
-            ekin, p = self.kinetic()
-            T = self.temperature(ekin)
+            ekin, p, T = ekin * lam * lam, p * lam, T * lam * lam
         self.step_count += 1
-        epot = float(self.E[0, 0])
         return {"step": self.step_count, "epot": epot, "ekin": ekin, "etot": epot + ekin, "T": T,
-                "momentum": p, "J": self.J[0].cpu().numpy().copy()}
+                "momentum": p, "J": J}
 
     def run(self, n: int, every: int = 1) -> list:
         out = []

@@ -453,6 +453,16 @@ struct AdjointTangents {
     static constexpr int value = (M <= 4 && sizeof(S) == 4) ? 6 : 3;
 };
 
+// pass(Base, K') for consecutive blocks of at most K of the NX parameters.
+template <int Base, int NX, int K, typename F>
+__device__ __forceinline__ void for_passes(F&& pass) {
+    if constexpr (Base < NX) {
+        constexpr int KK = (NX - Base) < K ? (NX - Base) : K;
+        pass(std::integral_constant<int, Base>{}, std::integral_constant<int, KK>{});
+        for_passes<Base + KK, NX, K>(pass);
+    }
+}
+
 template <typename S, int M, bool Full = false>
 __device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, const ItemCtx& x,
                                             unsigned char* __restrict__ lds) {
@@ -533,18 +543,9 @@ __device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, c
 #pragma unroll
             for (int t = 0; t < KK; ++t) phi[Base + t] += ke * U.d[t];
         };
-        using I = std::integral_constant<int, 0>;
 #pragma unroll
         for (int k = 0; k < NX; ++k) phi[k] = S(0);
-        static_assert(K == 3 || K == 6, "tangent blocks of 3 or 6");
-        if constexpr (K == 6) {
-            pass(I{}, std::integral_constant<int, 6>{});
-            if constexpr (Full) pass(std::integral_constant<int, 6>{}, std::integral_constant<int, 3>{});
-        } else {
-            pass(I{}, std::integral_constant<int, 3>{});
-            pass(std::integral_constant<int, 3>{}, std::integral_constant<int, 3>{});
-            if constexpr (Full) pass(std::integral_constant<int, 6>{}, std::integral_constant<int, 3>{});
-        }
+        for_passes<0, NX, K>(pass);
         exchange_sync(x.block_sync);
         double v[8];
 #pragma unroll

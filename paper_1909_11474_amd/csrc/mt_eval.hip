@@ -194,6 +194,51 @@ __global__ __launch_bounds__(256) void k_finalize_fit_wave(FinArgs F, int P) {
     }
 }
 
+// Z for sets without block-wide structures when S is small: one block per
+// candidate, one thread per structure (strided beyond the block), then a fixed
+// LDS tree.  Every thread issues its structure's table and partial-sum loads
+// at once, so a generation pays two memory round trips here instead of the
+// four or five of a wavefront looping over the structures.  OneSlot: every
+// structure has exactly one partial-sum slot (slot s), so the partial sums
+// load without the slot table, in the same round trip as the rest.
+template <bool OneSlot>
+__global__ __launch_bounds__(256) void k_finalize_fit_block(FinArgs F) {
+    __shared__ double sh[3][256];
+    const int c = blockIdx.x;
+    const SetDev& d = F.set;
+    double acc[3] = {0, 0, 0};
+    for (int s = threadIdx.x; s < d.S; s += blockDim.x) {
+        double e, w6[6], rf, j3[3];
+        if constexpr (OneSlot) {
+            const double* p = F.partial + ((size_t)c * d.nslots + s) * F.nv;
+            e = p[0];
+            for (int k = 0; k < 6; ++k) w6[k] = p[1 + k];
+            rf = p[7];
+        } else {
+            struct_sums(F, c, s, &e, w6, &rf, j3);
+        }
+        const double n = (double)(d.st_off[s + 1] - d.st_off[s]);
+        const double de = e / n - F.eref[s];
+        acc[0] += de * de;
+        for (int k = 0; k < 6; ++k) {
+            const double dw = w6[k] / n - F.wref[6 * s + k];
+            acc[1] += dw * dw;
+        }
+        acc[2] += rf;
+    }
+    block_sum3(acc, sh);
+    if (threadIdx.x == 0) {
+        const bool ok = cand_valid(F.x, c, F.full);
+        const double Ze = sqrt(acc[0] / F.Qe), Zv = sqrt(acc[1] / F.Qv), Zf = sqrt(acc[2] / F.Qf);
+        const double Z = F.we * Ze + F.wv * Zv + F.wf * Zf;
+        const double nan = __longlong_as_double(0x7ff8000000000000ll);
+        F.Z[4 * c + 0] = ok ? Z : nan;
+        F.Z[4 * c + 1] = ok ? Ze : nan;
+        F.Z[4 * c + 2] = ok ? Zv : nan;
+        F.Z[4 * c + 3] = ok ? Zf : nan;
+    }
+}
+
 // Gradient coefficients per (candidate, structure), from the forward partials
 // and Z: k_e, k_f, and C_s (xx yy zz yz zx xy, off-diagonals halved).
 __global__ __launch_bounds__(256) void k_grad_coef(FinArgs F) {
@@ -687,10 +732,20 @@ int launch_finalize_fit(mt_set* set, int P, const double* w, double* Z, hipStrea
     FinArgs F = make_fin(set, kNVFit, set->partial.as<double>());
     F.we = w[0]; F.wv = w[1]; F.wf = w[2];
     F.Z = Z;
-    if (F.coop)
+    if (F.coop) {
         hipLaunchKernelGGL(k_finalize_fit, dim3(P), dim3(256), 0, st, F);
-    else
+    } else if (set->S > 64) {
+        // power-of-two block (the LDS tree halves it), at least one thread per
+        // structure up to 256
+        int block = 128;
+        while (block < set->S && block < 256) block *= 2;
+        if (set->nslots == set->S)
+            hipLaunchKernelGGL(k_finalize_fit_block<true>, dim3(P), dim3(block), 0, st, F);
+        else
+            hipLaunchKernelGGL(k_finalize_fit_block<false>, dim3(P), dim3(block), 0, st, F);
+    } else {
         hipLaunchKernelGGL(k_finalize_fit_wave, dim3((P + 3) / 4), dim3(256), 0, st, F, P);
+    }
     HIPCHECK(hipGetLastError());
     return MT_OK;
 }

@@ -157,9 +157,11 @@ __global__ __launch_bounds__(256) void k_finalize_fit(FinArgs F) {
     }
 }
 
-// Z for sets without block-wide structures: one wavefront per candidate (four
-// per block), lanes over structures, then a fixed xor butterfly, after which
-// every lane holds the same sums.
+// Z for sets of at most 64 structures without block-wide ones: one wavefront
+// per candidate (four per block), lanes over structures, then a fixed xor
+// butterfly, after which every lane holds the same sums.  OneSlot as for
+// k_finalize_fit_block below.
+template <bool OneSlot>
 __global__ __launch_bounds__(256) void k_finalize_fit_wave(FinArgs F, int P) {
     const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -168,7 +170,14 @@ __global__ __launch_bounds__(256) void k_finalize_fit_wave(FinArgs F, int P) {
     double acc[3] = {0, 0, 0};
     for (int s = lane; s < d.S; s += 64) {
         double e, w6[6], rf, j3[3];
-        struct_sums(F, c, s, &e, w6, &rf, j3);
+        if constexpr (OneSlot) {
+            const double* p = F.partial + ((size_t)c * d.nslots + s) * F.nv;
+            e = p[0];
+            for (int k = 0; k < 6; ++k) w6[k] = p[1 + k];
+            rf = p[7];
+        } else {
+            struct_sums(F, c, s, &e, w6, &rf, j3);
+        }
         const double n = (double)(d.st_off[s + 1] - d.st_off[s]);
         const double de = e / n - F.eref[s];
         acc[0] += de * de;
@@ -744,7 +753,10 @@ int launch_finalize_fit(mt_set* set, int P, const double* w, double* Z, hipStrea
         else
             hipLaunchKernelGGL(k_finalize_fit_block<false>, dim3(P), dim3(block), 0, st, F);
     } else {
-        hipLaunchKernelGGL(k_finalize_fit_wave, dim3((P + 3) / 4), dim3(256), 0, st, F, P);
+        if (set->nslots == set->S)
+            hipLaunchKernelGGL(k_finalize_fit_wave<true>, dim3((P + 3) / 4), dim3(256), 0, st, F, P);
+        else
+            hipLaunchKernelGGL(k_finalize_fit_wave<false>, dim3((P + 3) / 4), dim3(256), 0, st, F, P);
     }
     HIPCHECK(hipGetLastError());
     return MT_OK;

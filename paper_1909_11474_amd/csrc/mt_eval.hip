@@ -45,6 +45,24 @@ __device__ __forceinline__ void block_sum3(double* a, double (*sh)[256]) {
     for (int k = 0; k < 3; ++k) a[k] = sh[k][0];
 }
 
+// The same sums by an xor butterfly inside each wavefront, then the
+// wavefront totals added in wavefront order (fixed, so deterministic).
+__device__ __forceinline__ void block_sum3_waves(double* a, double (*sh)[256]) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a[k] += __shfl_xor(a[k], o, 64);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 3; ++k) sh[k][w] = a[k];
+    __syncthreads();
+    for (int k = 0; k < 3; ++k) {
+        double t = sh[k][0];
+        for (int q = 1; q < nw; ++q) t += sh[k][q];
+        a[k] = t;
+    }
+}
+
 struct FinArgs {
     SetDev set;
     const double* partial;
@@ -235,7 +253,7 @@ __global__ __launch_bounds__(256) void k_finalize_fit_block(FinArgs F) {
         }
         acc[2] += rf;
     }
-    block_sum3(acc, sh);
+    block_sum3_waves(acc, sh);
     if (threadIdx.x == 0) {
         const bool ok = cand_valid(F.x, c, F.full);
         const double Ze = sqrt(acc[0] / F.Qe), Zv = sqrt(acc[1] / F.Qv), Zf = sqrt(acc[2] / F.Qf);

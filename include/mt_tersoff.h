@@ -7,9 +7,11 @@
  * candidate parameter set of a genetic-algorithm population and every training
  * structure, and returns energies, forces and virials (Sec. II) or the weighted
  * relative-RMSE fitness Z = w_e Z_e + w_v Z_v + w_f Z_f (Sec. III.B) and its
- * gradient with respect to the six parameters.  One GPU kernel covers all
- * candidate x structure pairs of a call, as the GPU implementation of
- * Sec. III.C describes.
+ * gradient with respect to the six parameters; the same for the
+ * nine-parameter Tersoff form (the *_tf entry points).  One GPU kernel covers
+ * all candidate x structure pairs of a call, as the GPU implementation of
+ * Sec. III.C describes.  Position updates and velocity-Verlet kernels serve
+ * the molecular dynamics the potential is built for (Sec. IV.C).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -28,7 +30,8 @@
  *   unless stated otherwise.
  * Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
  *   Evaluation calls are enqueued on it and return without synchronising;
- *   set creation and reference attachment synchronise it.
+ *   set creation, reference attachment, mt_set_update_positions and
+ *   mt_set_list_skin synchronise it.
  * Errors: every call returns MT_OK (0) or a negative mt_status; mt_last_error()
  *   then gives a message for the calling thread.  Argument errors are detected
  *   before any work is enqueued.  A candidate whose parameters are outside the
@@ -37,7 +40,7 @@
  *   unaffected.
  * Threads: an mt_set may be used from one thread at a time.
  *
- * Tersoff form: tersoff_eval_tf and fitness_eval_tf take the nine-parameter
+ * Tersoff form: tersoff_eval_tf, fitness_eval_tf and fitness_grad_tf take the nine-parameter
  * form of Sec. II.A (Eqs. 2-9 with Tersoff's angular function, Eq. 8) written
  * through Eqs. 11-14 with a free slope S:
  *   x[p*9 + k], k = 0..8 = D0 (eV), alpha (1/A), r0 (A), S, gamma, n, c, d, h;

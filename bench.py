@@ -196,6 +196,15 @@ def time_generations(torch, ts, X, Z, steps, warmup):
     torch.cuda.synchronize()
     prof = ts.profile_read()["batched"]
     ts.profile(False)
+    # per-generation times (an event pair around each call), for the median
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(max(20, min(steps, 200)))]
+    for a, b in ev:
+        a.record()
+        call()
+        b.record()
+    torch.cuda.synchronize()
+    t.median_ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
     return t, prof
 
 
@@ -408,13 +417,22 @@ def force_call(args, api, torch, W, dev):
            "outputs": "energy, forces, virial, per-atom virial, heat current",
            "set_create_ms": t_create * 1e3}
     for prec in ("fp32", "fp64"):
-        ts.tersoff_eval(wl.population, precision=prec, atom_virial=True, velocities=vel)
+        call = ts.eval_call(wl.population, precision=prec, atom_virial=True, velocities=vel)
+        call()
         with Timer(torch) as t:
             for _ in range(args.md_steps):
-                ts.tersoff_eval(wl.population, precision=prec, atom_virial=True, velocities=vel)
+                call()
+        # one call from an idle stream: host enqueue to completion
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        call()
+        torch.cuda.synchronize()
+        single = time.perf_counter() - t0
         out[prec] = {"ms_per_call": t.seconds / args.md_steps * 1e3,
-                     "atoms_per_s": s.n_atoms * args.md_steps / t.seconds}
-        log(f"64k force call {prec}: {out[prec]['ms_per_call']:.3f} ms/call")
+                     "atoms_per_s": s.n_atoms * args.md_steps / t.seconds,
+                     "single_call_ms": single * 1e3}
+        log(f"64k force call {prec}: {out[prec]['ms_per_call']:.3f} ms/call back to back, "
+            f"{single * 1e3:.3f} ms for one call")
     ts.close()
     return out
 
@@ -539,6 +557,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_median": t.median_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -198,6 +198,12 @@ class TersoffSet:
         device buffers (a GA generation loop): the arguments are converted once."""
         return FitnessCall(self, x, Z, weights, precision, schedule)
 
+    def eval_call(self, x, precision="fp32", atom_virial=False, velocities=None) -> "EvalCall":
+        """A pre-marshalled tersoff_eval (energies, forces, virials; per-atom
+        virials and heat current on request) into buffers allocated once, for
+        repeated force calls on the same parameters (molecular dynamics)."""
+        return EvalCall(self, x, precision, atom_virial, velocities)
+
     def fitness_grad(self, x, weights=(1.0, 1.0, 1.0), precision="fp32"):
         """(Z [P, 4], dZ/dx [P, 6]) as device tensors; for Tersoff-form x [P, 9]
         (fitness_grad_tf) dZ/dx is [P, 9]."""
@@ -258,6 +264,46 @@ class FitnessCall:
         if rc:
             L.check(rc, self._name)
         return self.Z
+
+
+class EvalCall:
+    """tersoff_eval (or tersoff_eval_tf) bound to buffers allocated once.
+    Calling it enqueues one evaluation on the current stream and returns the
+    output tensors (overwritten by the next call)."""
+
+    def __init__(self, tset: TersoffSet, x, precision, atom_virial, velocities):
+        self.tset = tset
+        self.x = tset._x(x)
+        P = self.x.shape[0]
+        kw = dict(dtype=torch.float64, device=tset.device)
+        self.E = torch.empty(P, tset.S, **kw)
+        self.F = torch.empty(P, 3, tset.N, **kw)
+        self.W = torch.empty(P, tset.S, 6, **kw)
+        self.Wi = torch.empty(P, 9, tset.N, **kw) if atom_virial else None
+        self.vel = None
+        self.J = None
+        if velocities is not None:
+            v = torch.as_tensor(np.asarray(velocities, dtype=np.float64)
+                                if not torch.is_tensor(velocities) else velocities)
+            self.vel = v.to(torch.float64).t().contiguous().to(tset.device)
+            self.J = torch.empty(P, 3, **kw)
+        self._name = "tersoff_eval_tf" if self.x.shape[1] == 9 else "tersoff_eval"
+        self._fn = getattr(tset._lib, self._name)
+        self._args = (tset._handle, _ptr(self.x), int(P), _prec(precision), L.MT_BATCHED,
+                      _ptr(self.E), _ptr(self.F), _ptr(self.W), _ptr(self.Wi), _ptr(self.vel),
+                      _ptr(self.J))
+
+    def __call__(self, stream: Optional[torch.cuda.Stream] = None):
+        s = stream if stream is not None else torch.cuda.current_stream(self.tset.device)
+        rc = self._fn(*self._args, ctypes.c_void_p(s.cuda_stream))
+        if rc:
+            L.check(rc, self._name)
+        out = {"E": self.E, "F": self.F.transpose(1, 2), "W": self.W}
+        if self.Wi is not None:
+            out["Wi"] = self.Wi.view(-1, 3, 3, self.tset.N).permute(0, 3, 1, 2)
+        if self.J is not None:
+            out["J"] = self.J
+        return out
 
 
 def from_structures(structs, R1: float = 2.8, R2: float = 3.2, max_nbr: int = L.MT_MAX_NBR,

@@ -146,3 +146,21 @@ def test_verlet_skin_gives_the_same_trajectory(MDm):
     assert np.abs(md.velocities() - vo).max() <= 1e-10
     assert md.rebuilds < 40
     md.close()
+
+
+def test_eval_call_matches_tersoff_eval(MDm):
+    """The pre-marshalled force call returns the same bits as tersoff_eval."""
+    import torch
+    from paper_1909_11474_amd import api
+    pos, cell, m, v = thermal(2, 87)
+    ts = api.TersoffSet(pos, cell[None], [0, pos.shape[0]])
+    X = np.vstack([W.TABLE2_X, W.draw_params(rng(88), 1)])
+    ref = ts.tersoff_eval(X, precision="fp64", atom_virial=True, velocities=v)
+    call = ts.eval_call(X, precision="fp64", atom_virial=True, velocities=v)
+    for _ in range(2):
+        out = call()
+        for k in ("E", "F", "W", "Wi", "J"):
+            assert torch.equal(out[k], ref[k]), k
+    X9 = W.draw_params_full(rng(89), 2)
+    assert torch.equal(ts.eval_call(X9, precision="fp64")()["E"], ts.tersoff_eval(X9, precision="fp64")["E"])
+    ts.close()

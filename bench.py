@@ -428,11 +428,35 @@ def force_call(args, api, torch, W, dev):
         call()
         torch.cuda.synchronize()
         single = time.perf_counter() - t0
+        ref = {k: v.clone() for k, v in call().items()}
+        # 100 calls captured in one HIP graph (the work lists and buffers exist
+        # before capture, and the evaluation path records no memset nodes)
+        g = torch.cuda.CUDAGraph()
+        cs = torch.cuda.Stream()
+        cs.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cs):
+            call()
+        torch.cuda.current_stream().wait_stream(cs)
+        with torch.cuda.graph(g):
+            for _ in range(100):
+                call()
+        g.replay()
+        torch.cuda.synchronize()
+        with Timer(torch) as tg:
+            g.replay()
+        same = all(torch.equal(v, ref[k]) for k, v in call().items())
+        g.replay()
+        torch.cuda.synchronize()
+        same = same and all(torch.equal(v, ref[k]) for k, v in
+                            {"E": call.E, "F": call.F.transpose(1, 2), "W": call.W}.items())
         out[prec] = {"ms_per_call": t.seconds / args.md_steps * 1e3,
                      "atoms_per_s": s.n_atoms * args.md_steps / t.seconds,
-                     "single_call_ms": single * 1e3}
+                     "single_call_ms": single * 1e3,
+                     "graph_100_calls_ms_per_call": tg.seconds / 100 * 1e3 if same else None}
         log(f"64k force call {prec}: {out[prec]['ms_per_call']:.3f} ms/call back to back, "
-            f"{single * 1e3:.3f} ms for one call")
+            f"{single * 1e3:.3f} ms for one call, "
+            f"{tg.seconds / 100 * 1e3:.3f} ms/call in a 100-call graph (replays {'match' if same else 'DIFFER'})")
+        del g
     ts.close()
     return out
 

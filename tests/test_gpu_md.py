@@ -164,3 +164,35 @@ def test_eval_call_matches_tersoff_eval(MDm):
     X9 = W.draw_params_full(rng(89), 2)
     assert torch.equal(ts.eval_call(X9, precision="fp64")()["E"], ts.tersoff_eval(X9, precision="fp64")["E"])
     ts.close()
+
+
+def test_force_calls_replay_in_a_graph(MDm):
+    """Ten pre-marshalled force calls captured in one HIP graph replay to the
+    eager result, with eager work between the replays."""
+    import torch
+    from paper_1909_11474_amd import api
+    pos, cell, m, v = thermal(3, 90)
+    ts = api.TersoffSet(pos, cell[None], [0, pos.shape[0]])
+    call = ts.eval_call(np.array(W.TABLE2_X), precision="fp32", atom_virial=True, velocities=v)
+    ref = {k: t.clone() for k, t in call().items()}
+    other = ts.eval_call(W.draw_params(rng(91), 2), precision="fp64")
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        call()
+    torch.cuda.current_stream().wait_stream(cs)
+    with torch.cuda.graph(g):
+        for _ in range(10):
+            call()
+    for _ in range(3):
+        call.E.zero_(); call.F.zero_(); call.Wi.zero_(); call.J.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(call.E, ref["E"]) and torch.equal(call.F.transpose(1, 2), ref["F"])
+        assert torch.equal(call.Wi.view(1, 3, 3, -1).permute(0, 3, 1, 2), ref["Wi"])
+        assert torch.equal(call.J, ref["J"])
+        other()                                          # eager work between replays
+        torch.cuda.synchronize()
+    del g
+    ts.close()

@@ -67,6 +67,17 @@ def measured_traffic():
     return PMC_TRAFFIC["fetch_bytes"] + PMC_TRAFFIC["write_bytes"]
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -541,20 +552,34 @@ def main():
         refs = {"e": e_ref.cpu().numpy(), "w": w_ref.cpu().numpy(), "f": f_ref.cpu().numpy()}
         top = T.topology(s, wl.R2)
         T.fitness(s, wl.population[:1], refs, topology=top)           # warm-up
-        # candidates in population order, wrapping round, until the budget is spent
-        done = 0
-        c0 = time.perf_counter()
-        while done == 0 or time.perf_counter() - c0 < args.cpu_seconds:
-            k = done % P
-            T.fitness(s, wl.population[k:k + 1], refs, topology=top)
-            done += 1
-        tc = time.perf_counter() - c0
+        def sample(seconds):
+            # candidates in population order, wrapping round, until the budget is spent
+            done = 0
+            c0 = time.perf_counter()
+            while done == 0 or time.perf_counter() - c0 < seconds:
+                k = done % P
+                T.fitness(s, wl.population[k:k + 1], refs, topology=top)
+                done += 1
+            return done, time.perf_counter() - c0
+
+        done, tc = sample(args.cpu_seconds)
         cpu = {"value": done * s.n_atoms / tc, "unit": "atom·candidate evals/s",
                "cores": int(torch.get_num_threads()), "kind": "oracle",
                "sample": f"{done} candidate evaluations (population of {P}, in order, wrapping) x "
                          f"all {s.n_struct} structures = {done * s.n_atoms} atom*candidate evals "
-                         f"in {tc:.1f} s, float64 autograd"}
+                         f"in {tc:.1f} s, float64 autograd",
+               "host": {"nproc": os.cpu_count(), "cpu_model": cpu_model()}}
         log(f"cpu oracle: {cpu['value']:.4e} atom*cand/s on {cpu['cores']} threads")
+        # the same oracle on one thread (a third of the budget)
+        threads = torch.get_num_threads()
+        torch.set_num_threads(1)
+        try:
+            done1, tc1 = sample(args.cpu_seconds / 3)
+        finally:
+            torch.set_num_threads(threads)
+        cpu["one_thread"] = {"value": done1 * s.n_atoms / tc1, "cores": 1,
+                             "sample": f"{done1} candidate evaluations in {tc1:.1f} s"}
+        log(f"cpu oracle, one thread: {cpu['one_thread']['value']:.4e} atom*cand/s")
     ts.close()
 
     workloads = {}

@@ -396,13 +396,13 @@ bool family_adjoint(int fam) {
     return fam == FAM_ADJ32 || fam == FAM_ADJ64 || fam == FAM_ADJ32F || fam == FAM_ADJ64F;
 }
 
-// LDS of one item: parameter records, bond-gradient exchange slots (4 values
-// each) and, for the adjoint, the force-residual exchange.
-size_t item_lds(const mt_set* set, int s, int block, int fam, int ptile) {
+// LDS of one item of nc candidates: parameter records, bond-gradient exchange
+// slots (4 values each) and, for the adjoint, the force-residual exchange.
+size_t item_lds(const mt_set* set, int s, int block, int fam, int nc) {
     const int npad = set->h_npad[s];
     const int R = block / npad;
     const size_t e = (size_t)family_elem(fam);
-    const size_t par = ((size_t)ptile * kNParam * e + 31) & ~(size_t)31;
+    const size_t par = ((size_t)nc * kNParam * e + 31) & ~(size_t)31;
     const size_t xs = (size_t)R * set->h_xsize[s] * 4 * e;
     const size_t ad = family_adjoint(fam) ? (size_t)R * npad * 4 * e : 0;
     return par + xs + ad;
@@ -535,7 +535,6 @@ ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int fam) {
     struct Group {
         std::vector<Item> items;
         size_t lds = 16;
-        int ptile = 1;
     };
     for (int mc : family_classes(fam)) {
         std::map<int, Group> groups;          // launch block size -> work items
@@ -551,7 +550,6 @@ ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int fam) {
             const int R = block / npad;
             const int tile = tile_for(cfg, P, R, plain);
             Group& g = groups[block];
-            g.ptile = std::max(g.ptile, std::min(tile, P));
             g.lds = std::max(g.lds, item_lds(set, s, block, fam, std::min(tile, P)));
             const int ns = set->h_off[s + 1] - set->h_off[s];
             for (int c0 = 0; c0 < P; c0 += tile) {
@@ -571,7 +569,6 @@ ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int fam) {
             cp->mc = mc;
             cp->block = it->first;
             cp->lds = it->second.lds;
-            cp->ptile = it->second.ptile;
             std::vector<int> bin_off;
             std::vector<Item> ordered;
             if (plain) {
@@ -625,7 +622,6 @@ static int run_plan(mt_set* set, ItemPlan* plan, const LaunchCfg& cfg, int fam, 
     const bool plain = cfg.block == 0;
     for (auto& cpp : plan->cls) {
         ClassPlan& cp = *cpp;
-        Af.ptile = Ad.ptile = cp.ptile;
         if (!plain) {
             Af.items = Ad.items = cp.items.as<Item>();
             Af.bin_off = Ad.bin_off = cp.bin_off.as<int>();

@@ -52,7 +52,6 @@ struct ClassPlan {            // work list of one launch: a coordination class a
     std::vector<Item> h_items;
     int n_items = 0;
     int n_bins = 0;
-    int ptile = 1;            // largest candidate count of an item
     size_t lds = 0;           // dynamic LDS bytes
 };
 

@@ -139,7 +139,6 @@ struct BArgs {
     const double* x;          // [P][6] (minimal) or [P][9] (Tersoff form) parameter sets
     double* partial;          // [P][nslots][nv]
     int nv;
-    int ptile;                // largest candidate count of an item in this launch
     // MODE_EVAL outputs (caller numbering); may be null
     double* force;            // [P][3][N]
     double* atom_virial;      // [P][9][N]
@@ -227,11 +226,14 @@ __device__ __forceinline__ void store_group(double* v, const ItemCtx& x, bool gr
         partial[((size_t)c * nslots + x.slot) * nv + off + vidx] = sum;
 }
 
-// LDS layout of a block: [ptile x kNParam parameter records][R x xsz exchange
-// slots (Vec4)][adjoint: R x npad force residuals (Vec4)].
+// LDS layout of a block while it works on an item: [it.nc x kNParam parameter
+// records][R x xsz exchange slots (Vec4)][adjoint: R x npad force residuals
+// (Vec4)].  The exchange follows the item's own records, so the LDS a launch
+// gets for the largest (records + exchange) of its structures covers every
+// item, whatever the candidate tiles of the other structures in the launch.
 template <typename S>
-__device__ __forceinline__ size_t lds_param_bytes(int ptile) {
-    return ((size_t)ptile * kNParam * sizeof(S) + 31) & ~(size_t)31;
+__device__ __forceinline__ size_t lds_param_bytes(int nc) {
+    return ((size_t)nc * kNParam * sizeof(S) + 31) & ~(size_t)31;
 }
 
 template <typename S, int MODE, int M, int GF = 0, bool Full = false>
@@ -240,7 +242,7 @@ __device__ __forceinline__ void run_batched(const BArgs<S>& A, const Item& it, c
     const SetDev& d = A.set;
     const int N = d.N;
     const S* __restrict__ pbuf = reinterpret_cast<const S*>(lds);
-    Vec4<S>* __restrict__ xb = reinterpret_cast<Vec4<S>*>(lds + lds_param_bytes<S>(A.ptile));
+    Vec4<S>* __restrict__ xb = reinterpret_cast<Vec4<S>*>(lds + lds_param_bytes<S>(it.nc));
     Geo<S, M> g;
     g.load(geom_of<S>(d), N, x.atom, x.active);
     constexpr int MM = M > 0 ? M : 1;
@@ -469,7 +471,7 @@ __device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, c
     const SetDev& d = A.set;
     const int N = d.N;
     const S* __restrict__ pbuf = reinterpret_cast<const S*>(lds);
-    Vec4<S>* __restrict__ xb = reinterpret_cast<Vec4<S>*>(lds + lds_param_bytes<S>(A.ptile));
+    Vec4<S>* __restrict__ xb = reinterpret_cast<Vec4<S>*>(lds + lds_param_bytes<S>(it.nc));
     Vec4<S>* __restrict__ ab = xb + (size_t)x.R * x.xsz + (size_t)x.q * x.npad;
     Geo<S, M> g;
     g.load(geom_of<S>(d), N, x.atom, x.active);

@@ -241,3 +241,44 @@ def test_ga_over_nine_genes_on_the_gpu_fitness(api):
     zo = T.fitness(s, x[None], refs, topology=T.topology(s, R2))[0, 0]
     assert abs(z - zo) <= 1e-5 * abs(zo) + 1e-6
     ts.close()
+
+
+
+@pytest.mark.parametrize("form", ["minimal", "tersoff"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_launch_shapes_on_a_mixed_set_give_identical_fitness(api, tmp_path, precision, form):
+    """Block size, candidate tile and persistent bins change only the schedule,
+    also where one launch holds structures of different padded sizes and hence
+    different candidate tiles (64-atom cells at 2 replicas per 128-thread block
+    next to clusters at 16): Z is bit-identical across shapes and to the plain
+    path, for both parameterisations.  A launch whose LDS were sized for one
+    structure's records and another's exchange slots would lose the last
+    replica's slots and show here as wrong force residuals."""
+    s = mixed_set(with_large=False)
+    draw = W.draw_params if form == "minimal" else W.draw_params_full
+    hidden = draw(rng(79), 1)[0]
+    refs = T.reference_data(s, hidden, R1, R2)
+    ts = api.from_structures(s)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    X = draw(rng(80), 20)
+    P = X.shape[0]
+    ref = ts.fitness(X, precision=precision, schedule="plain").cpu().numpy()
+    if precision == "fp64":
+        idx = [0, 1, 7]
+        Zo = T.fitness(s, X[idx], refs, topology=T.topology(s, R2))
+        assert np.abs(ref[idx] - Zo).max() <= 1e-10 * np.abs(Zo).max()
+    st = ts.stats()
+    prec = 0 if precision == "fp64" else 1
+    key = (f"N={st['n_atoms']} S={st['n_struct']} nb={st['n_bonds']} trip={st['n_triplets']} "
+           f"P={P} prec={prec}")
+    k = 0
+    for block in (128, 256, 512):
+        for tile in (1, 8, 32):
+            for persistent in (0, 1):
+                k += 1
+                cache = tmp_path / f"c{k}.txt"
+                cache.write_text(f"{key} | block={block} tile={tile} persistent={persistent} ms=0\n")
+                ts.autotune(P, precision, str(cache))
+                Z = ts.fitness(X, precision=precision).cpu().numpy()
+                assert np.array_equal(Z, ref), (block, tile, persistent)
+    ts.close()

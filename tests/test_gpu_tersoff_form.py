@@ -251,9 +251,11 @@ def test_launch_shapes_on_a_mixed_set_give_identical_fitness(api, tmp_path, prec
     also where one launch holds structures of different padded sizes and hence
     different candidate tiles (64-atom cells at 2 replicas per 128-thread block
     next to clusters at 16): Z is bit-identical across shapes and to the plain
-    path, for both parameterisations.  A launch whose LDS were sized for one
-    structure's records and another's exchange slots would lose the last
-    replica's slots and show here as wrong force residuals."""
+    path, and dZ/dx (the adjoint kernels, same work lists) is bit-identical
+    across shapes and matches the oracle, for both parameterisations.  A launch
+    whose LDS were sized for one structure's records and another's exchange
+    slots would lose the last replica's slots and show here as wrong force
+    residuals."""
     s = mixed_set(with_large=False)
     draw = W.draw_params if form == "minimal" else W.draw_params_full
     hidden = draw(rng(79), 1)[0]
@@ -263,10 +265,11 @@ def test_launch_shapes_on_a_mixed_set_give_identical_fitness(api, tmp_path, prec
     X = draw(rng(80), 20)
     P = X.shape[0]
     ref = ts.fitness(X, precision=precision, schedule="plain").cpu().numpy()
+    idx = [1, 7]
+    Zo, Go = T.fitness_grad(s, X[idx], refs, topology=T.topology(s, R2))
     if precision == "fp64":
-        idx = [0, 1, 7]
-        Zo = T.fitness(s, X[idx], refs, topology=T.topology(s, R2))
         assert np.abs(ref[idx] - Zo).max() <= 1e-10 * np.abs(Zo).max()
+    G0 = None
     st = ts.stats()
     prec = 0 if precision == "fp64" else 1
     key = (f"N={st['n_atoms']} S={st['n_struct']} nb={st['n_bonds']} trip={st['n_triplets']} "
@@ -281,4 +284,11 @@ def test_launch_shapes_on_a_mixed_set_give_identical_fitness(api, tmp_path, prec
                 ts.autotune(P, precision, str(cache))
                 Z = ts.fitness(X, precision=precision).cpu().numpy()
                 assert np.array_equal(Z, ref), (block, tile, persistent)
+                G = ts.fitness_grad(X, precision=precision)[1].cpu().numpy()
+                if G0 is None:
+                    G0 = G
+                    tol = 1e-10 if precision == "fp64" else 1e-4
+                    for c, go in zip(idx, Go):
+                        assert np.abs(G[c] - go).max() <= tol * np.abs(go).max(), c
+                assert np.array_equal(G, G0), (block, tile, persistent)
     ts.close()

@@ -220,6 +220,42 @@ def test_uneven_subset_fitness_vs_oracle(api, uneven, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_uneven_subset_launch_shapes(api, uneven, tmp_path, precision):
+    """The 18-structure subset (8 to 512 atoms, padded sizes 8 to 512, so one
+    launch mixes replica counts and candidate tiles, and the largest
+    structures fall back to smaller blocks or the two-pass path): Z and dZ/dx
+    bit-identical across candidate tiles and persistent bins at block 512,
+    Z also to the plain schedule in float64."""
+    sub = uneven_subset(uneven)
+    refs = T.reference_data(sub, uneven.hidden_x, R1, R2)
+    ts = api.from_structures(sub)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    X = uneven.population[:24]
+    P = X.shape[0]
+    st = ts.stats()
+    prec = 0 if precision == "fp64" else 1
+    key = (f"N={st['n_atoms']} S={st['n_struct']} nb={st['n_bonds']} trip={st['n_triplets']} "
+           f"P={P} prec={prec}")
+    Zp = ts.fitness(X, precision=precision, schedule="plain").cpu().numpy()
+    Z0 = G0 = None
+    for k, (tile, persistent) in enumerate([(t, p) for t in (1, 4, 8, 24) for p in (0, 1)]):
+        cache = tmp_path / f"c{k}.txt"
+        cache.write_text(f"{key} | block=512 tile={tile} persistent={persistent} ms=0\n")
+        ts.autotune(P, precision, str(cache))
+        Z = ts.fitness(X, precision=precision).cpu().numpy()
+        G = ts.fitness_grad(X, precision=precision)[1].cpu().numpy()
+        if Z0 is None:
+            Z0, G0 = Z, G
+            if precision == "fp64":
+                assert np.array_equal(Z, Zp)
+            else:
+                assert rel_err(Z, Zp, 1e-12) <= 1e-6
+        assert np.array_equal(Z, Z0), (tile, persistent)
+        assert np.array_equal(G, G0), (tile, persistent)
+    ts.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_uneven_subset_gradient_vs_oracle(api, uneven, precision):
     sub = uneven_subset(uneven)
     refs = T.reference_data(sub, uneven.hidden_x, R1, R2)

@@ -30,8 +30,8 @@
  *   unless stated otherwise.
  * Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
  *   Evaluation calls are enqueued on it and return without synchronising;
- *   set creation, reference attachment, mt_set_update_positions and
- *   mt_set_list_skin synchronise it.
+ *   set creation, reference attachment, mt_set_update_positions,
+ *   mt_set_list_skin and mt_profile_fitness_kernels synchronise it.
  * Errors: every call returns MT_OK (0) or a negative mt_status; mt_last_error()
  *   then gives a message for the calling thread.  Argument errors are detected
  *   before any work is enqueued.  A candidate whose parameters are outside the
@@ -304,6 +304,23 @@ int mt_autotune(mt_set* set, int P, int precision, const char* cache_path);
  */
 int mt_profile_enable(mt_set* set, int enable);
 int mt_profile_read(mt_set* set, double* ms, int64_t* launches);
+
+/*
+ * Back-to-back timing of the batched fitness kernels, for roofline figures:
+ * the kernel launches that fitness_eval (nx = 6) or fitness_eval_tf (nx = 9)
+ * makes for P candidates at this precision and launch shape (two-pass
+ * structures and the finalize excluded) are issued reps times in a row on
+ * the stream between one pair of HIP events, so the dispatch latency that an
+ * event pair around each launch adds is paid once instead of per launch.
+ *   x         device double [P][nx], as for fitness_eval / fitness_eval_tf
+ *   ms        host double: average milliseconds per pass
+ *   launches  host int64: kernel launches per pass
+ * Overwrites the set's partial sums (not Z); synchronises the stream.
+ * Errors: MT_EINVAL for a NULL pointer, nx not 6 or 9, P or reps <= 0;
+ * MT_ENOREF without reference data; MT_EHIP if a HIP call fails.
+ */
+int mt_profile_fitness_kernels(mt_set* set, const double* x, int nx, int P, int precision, int reps,
+                               double* ms, int64_t* launches, void* stream);
 
 /* Message for the calling thread's most recent error (never NULL). */
 const char* mt_last_error(void);

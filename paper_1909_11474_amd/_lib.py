@@ -57,6 +57,8 @@ SIGNATURES = {
     "mt_autotune": (_i, [_vp, _i, _i, ctypes.c_char_p]),
     "mt_profile_enable": (_i, [_vp, _i]),
     "mt_profile_read": (_i, [_vp, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_int64)]),
+    "mt_profile_fitness_kernels": (_i, [_vp, _vp, _i, _i, _i, _i, ctypes.POINTER(_d),
+                                        ctypes.POINTER(ctypes.c_int64), _vp]),
     "mt_last_error": (ctypes.c_char_p, []),
     "mt_version": (ctypes.c_char_p, []),
 }

@@ -230,6 +230,20 @@ class TersoffSet:
         L.check(self._lib.mt_profile_read(self._handle, ms, n), "mt_profile_read")
         return {"batched": (ms[0], int(n[0])), "adjoint": (ms[1], int(n[1]))}
 
+    def profile_fitness_kernels(self, x, precision="fp32", reps: int = 100):
+        """(ms per pass, launches per pass) of reps back-to-back passes of the
+        batched fitness kernels for x [P, 6] or [P, 9], between one event pair."""
+        xt = self._x(x)
+        P, nx = xt.shape
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        with torch.cuda.device(self.device):
+            rc = self._lib.mt_profile_fitness_kernels(self._handle, _ptr(xt), nx, P, _prec(precision),
+                                                      int(reps), ctypes.byref(ms), ctypes.byref(n),
+                                                      self._stream())
+        L.check(rc, "mt_profile_fitness_kernels")
+        return ms.value, int(n.value)
+
     def autotune(self, P: int, precision="fp32", cache_path: Optional[str] = None):
         with torch.cuda.device(self.device):
             rc = self._lib.mt_autotune(self._handle, int(P), _prec(precision),

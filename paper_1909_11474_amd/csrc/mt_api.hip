@@ -413,6 +413,20 @@ int mt_profile_enable(mt_set* set, int enable) {
     return MT_OK;
 }
 
+int mt_profile_fitness_kernels(mt_set* set, const double* x, int nx, int P, int precision, int reps,
+                               double* ms, int64_t* launches, void* stream) {
+    TRY(check_common(set, x, P, precision));
+    if (nx != 6 && nx != 9) return fail(MT_EINVAL, "nx must be 6 (minimal) or 9 (Tersoff form)");
+    if (reps <= 0) return fail(MT_EINVAL, "reps must be positive");
+    if (!ms || !launches) return fail(MT_EINVAL, "ms and launches must not be NULL");
+    if (!set->has_ref) return fail(MT_ENOREF, "no reference data attached to the set");
+    TRY(ensure_workspace(set, P, kNVFit));
+    set->cur_x = x;
+    set->cur_form = nx == 9 ? 1 : 0;
+    return time_batched_kernels(set, cfg_for(set, P, precision), P, precision, reps,
+                                (hipStream_t)stream, ms, launches);
+}
+
 int mt_profile_read(mt_set* set, double* ms, int64_t* launches) {
     if (!set || !ms || !launches) return fail(MT_EINVAL, "NULL argument");
     for (int k = 0; k < 2; ++k) {

@@ -675,6 +675,40 @@ int launch_plain(mt_set* set, int P, int precision, int mode, const double* vel,
     return launch_batched(set, plain, P, precision, mode, vel, force, atom_virial, st);
 }
 
+// reps back-to-back passes of the batched fitness kernels (the launches of
+// run_plan only: no two-pass structures, no finalize) between one event pair;
+// the per-pass average in ms and the launches per pass.  Synchronises st.
+int time_batched_kernels(mt_set* set, const LaunchCfg& cfg, int P, int precision, int reps,
+                         hipStream_t st, double* ms, int64_t* launches) {
+    const int fam = family_for(precision, MODE_FIT, set->cur_form);
+    ItemPlan* plan = get_plan(set, P, cfg, fam);
+    if (!plan) {
+        set_error("could not build the work list (block smaller than a structure?)");
+        return MT_EINVAL;
+    }
+    BArgs<float> Af = make_args<float>(set, set->partial.as<double>(), kNVFit);
+    BArgs<double> Ad = make_args<double>(set, set->partial.as<double>(), kNVFit);
+    hipEvent_t e[2] = {nullptr, nullptr};
+    int rc = MT_OK;
+    hipError_t he = hipSuccess;
+    for (auto& ev : e)
+        if (rc == MT_OK && (he = hipEventCreate(&ev)) != hipSuccess) rc = hip_fail(he, "hipEventCreate");
+    if (rc == MT_OK && (he = hipEventRecord(e[0], st)) != hipSuccess) rc = hip_fail(he, "hipEventRecord");
+    for (int r = 0; r < reps && rc == MT_OK; ++r) rc = run_plan(set, plan, cfg, fam, Af, Ad, 0, st);
+    if (rc == MT_OK && (he = hipEventRecord(e[1], st)) != hipSuccess) rc = hip_fail(he, "hipEventRecord");
+    if (rc == MT_OK && (he = hipEventSynchronize(e[1])) != hipSuccess) rc = hip_fail(he, "hipEventSynchronize");
+    float t = 0.f;
+    if (rc == MT_OK && (he = hipEventElapsedTime(&t, e[0], e[1])) != hipSuccess)
+        rc = hip_fail(he, "hipEventElapsedTime");
+    for (auto& ev : e)
+        if (ev) (void)hipEventDestroy(ev);
+    if (rc != MT_OK) return rc;
+    *ms = (double)t / reps;
+    *launches = 0;
+    for (auto& cp : plan->cls) *launches += cfg.block == 0 ? cp->n_items : 1;
+    return MT_OK;
+}
+
 // Candidates per launch of the two-pass path for structure s: bounded so that
 // the bond-gradient staging buffer stays within 256 MB.
 static int twopass_chunk(const mt_set* set, int s, int P, size_t elem) {

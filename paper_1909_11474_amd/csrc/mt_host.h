@@ -169,6 +169,9 @@ int launch_batched(mt_set* set, const LaunchCfg& cfg, int P, int precision, int 
                    const double* vel, double* force, double* atom_virial, hipStream_t stream);
 int launch_plain(mt_set* set, int P, int precision, int mode, const double* vel, double* force,
                  double* atom_virial, hipStream_t stream);
+// Average time of reps back-to-back passes of the batched fitness kernels.
+int time_batched_kernels(mt_set* set, const LaunchCfg& cfg, int P, int precision, int reps,
+                         hipStream_t stream, double* ms, int64_t* launches);
 int launch_large(mt_set* set, int P, int precision, int mode, const double* vel, double* force,
                  double* atom_virial, hipStream_t stream);
 // Reserve the two-pass staging buffer for the set's large structures and the

@@ -6,6 +6,8 @@ Tolerances (GPU vs oracle):
 * FP32 arithmetic with FP64 accumulation: |de_s| <= 1e-6 eV/atom,
   |dF| <= 1e-4 eV/A per component, |dw_s| <= 1e-5 eV/atom (virial per atom).
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -239,4 +241,33 @@ def test_repeated_graph_replays_are_identical(api):
     X.copy_(X2)
     changed = call().clone()
     assert not torch.equal(changed, first)
+    ts.close()
+
+
+def test_back_to_back_kernel_timing(api):
+    """mt_profile_fitness_kernels: one launch per pass for a set of 64-atom
+    cells, a positive time, Z of later fitness calls unchanged (graph replay
+    and direct), both parameterisations; error codes for bad arguments."""
+    import torch
+    from paper_1909_11474_amd import _lib as L
+    wl, refs = small_training(6)
+    ts = api.from_structures(wl.structs)
+    X = np.array(wl.population[:8])
+    with pytest.raises(L.MTError) as e:
+        ts.profile_fitness_kernels(X, "fp32", 4)
+    assert e.value.code == L.MT_ENOREF
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    Z0 = ts.fitness(X, precision="fp32").clone()
+    for x in (X, W.draw_params_full(np.random.Generator(np.random.PCG64(5)), 8)):
+        for precision in ("fp32", "fp64"):
+            ms, n = ts.profile_fitness_kernels(x, precision, 4)
+            assert n == 1 and 0.0 < ms < 1000.0, (ms, n)
+    assert torch.equal(ts.fitness(X, precision="fp32"), Z0)
+    xt = torch.as_tensor(X, device="cuda").contiguous()
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    for nx, reps in ((7, 4), (6, 0)):
+        rc = ts._lib.mt_profile_fitness_kernels(ts._handle, ctypes.c_void_p(xt.data_ptr()), nx, 8, 1,
+                                                reps, ctypes.byref(ms), ctypes.byref(n), None)
+        assert rc == L.MT_EINVAL, (nx, reps)
     ts.close()

@@ -525,7 +525,7 @@ ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int fam) {
     auto plan = std::make_unique<ItemPlan>();
     const bool plain = cfg.block == 0;
     int ncu = 256;
-    if (cfg.persistent) {
+    if (!plain) {
         int dev = 0;
         (void)hipGetDevice(&dev);
         hipDeviceProp_t prop;
@@ -536,10 +536,40 @@ ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int fam) {
         std::vector<Item> items;
         size_t lds = 16;
     };
-    for (int mc : family_classes(fam)) {
+    // Launch class of each structure.  A class above 4 whose work items would
+    // fill fewer blocks than the device has compute units joins the next
+    // larger class that has work: on its own its launch leaves most of the
+    // device idle, and the larger class's kernel runs the same compiled
+    // variants (chosen per wavefront by the largest coordination, never
+    // below 3) on the same exchange-slot layout, so results are unchanged.
+    const std::vector<int>& classes = family_classes(fam);
+    std::vector<int> cls(set->S, 0);
+    std::map<int, long long> nitems;
+    for (int s = 0; s < set->S; ++s) {
+        if (set->h_large[s]) continue;
+        cls[s] = class_of(fam, set->h_kmax[s]);
+        if (!plain) {
+            const int tile = tile_for(cfg, P, std::max(1, cfg.block / set->h_npad[s]), plain);
+            nitems[cls[s]] += (P + tile - 1) / tile;
+        }
+    }
+    for (size_t i = 0; !plain && i < classes.size(); ++i) {
+        const int mc = classes[i];
+        if (mc <= 4 || nitems[mc] == 0 || nitems[mc] >= ncu) continue;
+        for (size_t j = i + 1; j < classes.size(); ++j) {
+            const int to = classes[j];
+            if (nitems[to] == 0) continue;
+            for (int s = 0; s < set->S; ++s)
+                if (!set->h_large[s] && cls[s] == mc) cls[s] = to;
+            nitems[to] += nitems[mc];
+            nitems[mc] = 0;
+            break;
+        }
+    }
+    for (int mc : classes) {
         std::map<int, Group> groups;          // launch block size -> work items
         for (int s = 0; s < set->S; ++s) {
-            if (set->h_large[s] || class_of(fam, set->h_kmax[s]) != mc) continue;
+            if (set->h_large[s] || cls[s] != mc) continue;
             const int npad = set->h_npad[s];
             if (!plain && cfg.block < npad) return nullptr;
             const int block = block_for(set, s, cfg, P, fam, plain);

@@ -43,12 +43,14 @@ TUNED_SHAPES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1
 # WRITE_SIZE; KiB per dispatch) scaled by what the same counters read for a
 # 256 MiB device-to-device copy (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00), recorded
 # in profiles/k_batched_fit32_ga_batch_traffic.md.  Valid only for the kernel
-# sources it was measured on: reported when their hash still matches.
+# sources and the host file that places the work items (mt_eval.hip) it was
+# measured on: reported when their hash still matches.
 PMC_TRAFFIC = {
     "sources": ["paper_1909_11474_amd/csrc/mt_common.h", "paper_1909_11474_amd/csrc/mt_site.h",
-                "paper_1909_11474_amd/csrc/mt_kernels.h", "paper_1909_11474_amd/csrc/mt_k_fit32.hip"],
-    "sha256_16": "1acc0e9ec5913edc",
-    "fetch_bytes": 2467.4 * 1024 * 2.00,
+                "paper_1909_11474_amd/csrc/mt_kernels.h", "paper_1909_11474_amd/csrc/mt_k_fit32.hip",
+                "paper_1909_11474_amd/csrc/mt_eval.hip"],
+    "sha256_16": "7f930986759f6a97",
+    "fetch_bytes": 1969.3 * 1024 * 2.00,
     "write_bytes": 4250.0 * 1024 * 1.00,
 }
 

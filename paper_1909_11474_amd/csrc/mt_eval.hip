@@ -517,6 +517,32 @@ static int block_for(const mt_set* set, int s, const LaunchCfg& cfg, int P, int 
     return 0;
 }
 
+// The blocks of a launch go to the XCDs round robin (block b to XCD b mod 8),
+// and each XCD has its own L2.  Within every run of equal-cost items (the
+// order across runs is kept), order the items structure by structure and deal
+// each XCD a contiguous share of the run: the candidate tiles of a structure
+// then run on one XCD, and its bond geometry comes from HBM about once instead
+// of once per XCD it lands on.  Only the placement changes, not any result.
+static std::vector<Item> xcd_grouped(const std::vector<Item>& items) {
+    constexpr size_t kXcd = 8;
+    std::vector<Item> out(items.size());
+    size_t a = 0;
+    while (a < items.size()) {
+        size_t e = a;
+        while (e < items.size() && items[e].cost == items[a].cost) ++e;
+        std::vector<Item> run(items.begin() + a, items.begin() + e);
+        std::stable_sort(run.begin(), run.end(), [](const Item& x, const Item& y) {
+            return x.s != y.s ? x.s < y.s : x.c0 < y.c0;
+        });
+        size_t next = 0;
+        for (size_t k = 0; k < kXcd; ++k)
+            for (size_t b = a; b < e; ++b)
+                if (b % kXcd == k) out[b] = run[next++];
+        a = e;
+    }
+    return out;
+}
+
 // cfg.block == 0 requests the plain plan: one item per (structure, candidate).
 ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int fam) {
     auto key = std::make_tuple(P, cfg.block, cfg.tile, cfg.persistent, fam);
@@ -605,12 +631,11 @@ ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int fam) {
                 ordered = items;
                 bin_off = {0, 1};
             } else {
-                // candidate-tile-major among equal costs, so that the candidates of
-                // early tiles complete while later tiles run
-                std::stable_sort(items.begin(), items.end(),
-                                 [](const Item& a, const Item& b) { return a.c0 < b.c0; });
+                // longest first; equal costs grouped by XCD (bins, one per block,
+                // take the items in this order)
                 std::stable_sort(items.begin(), items.end(),
                                  [](const Item& a, const Item& b) { return a.cost > b.cost; });
+                items = xcd_grouped(items);
                 if (!cfg.persistent) {
                     ordered = items;
                     bin_off.resize(items.size() + 1);

@@ -16,7 +16,10 @@ only the bond geometry is recomputed (mt_set_update_geometry) until some atom
 has moved skin/2 since the last rebuild (mt_md_max_disp).
 
 Every step runs in the library's kernels; the host keeps only per-step
-scalars (potential energy, kinetic sums, J).
+scalars (potential energy, kinetic sums, J), read back with one copy per step
+(plus one for the displacement check with a skin).  The library calls' argument
+lists are marshalled once at construction, and the run uses the torch stream
+that is current then.
 """
 from __future__ import annotations
 
@@ -68,62 +71,75 @@ class MD:
         m = np.asarray(masses, dtype=np.float64)
         self.mass = torch.as_tensor(m, **kw)
         self.inv_mass = torch.as_tensor(1.0 / m, **kw)
-        self.E = torch.empty(1, 1, **kw)
+        # per-step scalars in one buffer: E [1][1], J [1][3], kinetic sums [4]
+        self._sc = torch.empty(8, **kw)
+        self._sc_host = torch.empty(8, dtype=torch.float64, pin_memory=True)
+        self._sc_np = self._sc_host.numpy()
+        self.E = self._sc[0:1].view(1, 1)
+        self.J = self._sc[1:4].view(1, 3)
+        self.kin = self._sc[4:8]
         self.F = torch.empty(1, 3, self.N, **kw)
         self.W = torch.empty(1, 1, 6, **kw)
         self.Wi = torch.empty(1, 9, self.N, **kw)
-        self.J = torch.empty(1, 3, **kw)
-        self.kin = torch.empty(4, **kw)
         self.fe = None if fe is None else (ctypes.c_double * 3)(*[float(v) for v in fe])
         self.fe_vec = None if fe is None else np.asarray(fe, dtype=np.float64)
         self.thermostat = thermostat       # (T0 in K, tau in fs) or None
         self.step_count = 0
         self.skin = float(skin)
         self.rebuilds = 0
+        self._tstream = torch.cuda.current_stream(self.dev)
+        self._st = ctypes.c_void_p(self._tstream.cuda_stream)
         if self.skin > 0:
-            L.check(self._lib.mt_set_list_skin(self.ts._handle, self.skin, self._stream()), "mt_set_list_skin")
+            L.check(self._lib.mt_set_list_skin(self.ts._handle, self.skin, self._st), "mt_set_list_skin")
             self.ref = self.pos.clone()
             self.disp = torch.empty(1, **kw)
+            self._disp_host = torch.empty(1, dtype=torch.float64, pin_memory=True)
+        self._marshal()
         self._forces()
 
     # -- library calls -------------------------------------------------------------
-    def _stream(self):
-        return ctypes.c_void_p(torch.cuda.current_stream(self.dev).cuda_stream)
-
     def _p(self, t):
         return ctypes.c_void_p(t.data_ptr())
 
-    def _forces(self):
-        L.check(self._eval(self.ts._handle, self._p(self.x), 1, self.prec, L.MT_BATCHED,
-                           self._p(self.E), self._p(self.F), self._p(self.W), self._p(self.Wi),
-                           self._p(self.vel), self._p(self.J), self._stream()), "tersoff_eval")
+    def _marshal(self):
+        """Argument lists of the per-step calls (every buffer is allocated once)."""
+        P, st, drive = self._p, self._st, self.fe is not None
+        self._a_forces = (self.ts._handle, P(self.x), 1, self.prec, L.MT_BATCHED, P(self.E), P(self.F),
+                          P(self.W), P(self.Wi), P(self.vel), P(self.J), st)
+        self._a_kick = (self.N, P(self.vel), P(self.F), P(self.Wi) if drive else None,
+                        P(self.W) if drive else None, self.fe if drive else None, P(self.inv_mass),
+                        ctypes.c_double(0.5 * self.dt), st)
+        self._a_drift = (self.N, P(self.pos), P(self.vel), ctypes.c_double(self.dt), st)
+        self._a_kinetic = (self.N, P(self.vel), P(self.mass), P(self.kin), st)
+        self._a_geometry = (self.ts._handle, P(self.pos), st)
+        if self.skin > 0:
+            self._a_disp = (self.N, P(self.pos), P(self.ref), P(self.disp), st)
+            self._disp_limit = (0.5 * self.skin) ** 2
 
-    def _kick(self, dt_half):
-        drive = self.fe is not None
-        L.check(self._lib.mt_md_kick(self.N, self._p(self.vel), self._p(self.F),
-                                     self._p(self.Wi) if drive else None,
-                                     self._p(self.W) if drive else None,
-                                     self.fe if drive else None, self._p(self.inv_mass),
-                                     float(dt_half), self._stream()), "mt_md_kick")
+    def _forces(self):
+        L.check(self._eval(*self._a_forces), "tersoff_eval")
+
+    def _kick(self):
+        L.check(self._lib.mt_md_kick(*self._a_kick), "mt_md_kick")
 
     def _update_positions(self):
         if self.skin > 0:
-            L.check(self._lib.mt_md_max_disp(self.N, self._p(self.pos), self._p(self.ref),
-                                             self._p(self.disp), self._stream()), "mt_md_max_disp")
-            if float(self.disp[0]) < (0.5 * self.skin) ** 2:
-                L.check(self._lib.mt_set_update_geometry(self.ts._handle, self._p(self.pos),
-                                                         self._stream()), "mt_set_update_geometry")
+            L.check(self._lib.mt_md_max_disp(*self._a_disp), "mt_md_max_disp")
+            with torch.cuda.stream(self._tstream):
+                self._disp_host.copy_(self.disp)             # synchronous
+            if float(self._disp_host[0]) < self._disp_limit:
+                L.check(self._lib.mt_set_update_geometry(*self._a_geometry), "mt_set_update_geometry")
                 return
-            self.ref.copy_(self.pos)
-        L.check(self._lib.mt_set_update_positions(self.ts._handle, self._p(self.pos), self._stream()),
-                "mt_set_update_positions")
+            with torch.cuda.stream(self._tstream):
+                self.ref.copy_(self.pos)
+        L.check(self._lib.mt_set_update_positions(*self._a_geometry), "mt_set_update_positions")
         self.rebuilds += 1
 
     def kinetic(self):
         """(kinetic energy in eV, total momentum [3] in u A/fs)."""
-        L.check(self._lib.mt_md_kinetic(self.N, self._p(self.vel), self._p(self.mass),
-                                        self._p(self.kin), self._stream()), "mt_md_kinetic")
-        k = self.kin.cpu().numpy()
+        L.check(self._lib.mt_md_kinetic(*self._a_kinetic), "mt_md_kinetic")
+        with torch.cuda.stream(self._tstream):
+            k = self.kin.cpu().numpy()
         return 0.5 * k[0] * MV2_TO_EV, k[1:].copy()
 
     def temperature(self, ekin: float) -> float:
@@ -131,23 +147,23 @@ class MD:
 
     # -- stepping ------------------------------------------------------------------
     def step(self) -> dict:
-        self._kick(0.5 * self.dt)
-        L.check(self._lib.mt_md_drift(self.N, self._p(self.pos), self._p(self.vel), self.dt,
-                                      self._stream()), "mt_md_drift")
+        lib = self._lib
+        self._kick()
+        L.check(lib.mt_md_drift(*self._a_drift), "mt_md_drift")
         self._update_positions()
         self._forces()
-        self._kick(0.5 * self.dt)
-        L.check(self._lib.mt_md_kinetic(self.N, self._p(self.vel), self._p(self.mass),
-                                        self._p(self.kin), self._stream()), "mt_md_kinetic")
-        # one read-back per step: E, J and the kinetic sums together
-        sc = torch.cat([self.E.view(-1), self.J.view(-1), self.kin]).cpu().numpy()
+        self._kick()
+        L.check(lib.mt_md_kinetic(*self._a_kinetic), "mt_md_kinetic")
+        # one read-back per step: E, J and the kinetic sums share one buffer
+        with torch.cuda.stream(self._tstream):
+            self._sc_host.copy_(self._sc)                     # synchronous
+        sc = self._sc_np
         epot, J, ekin, p = float(sc[0]), sc[1:4].copy(), 0.5 * sc[4] * MV2_TO_EV, sc[5:8].copy()
         T = self.temperature(ekin)
         if self.thermostat is not None:
             T0, tau = self.thermostat
             lam = np.sqrt(max(1.0 + self.dt / tau * (T0 / max(T, 1e-12) - 1.0), 0.0))
-            L.check(self._lib.mt_md_scale(self.N, self._p(self.vel), float(lam), self._stream()),
-                    "mt_md_scale")
+            L.check(self._lib.mt_md_scale(self.N, self._p(self.vel), float(lam), self._st), "mt_md_scale")
             ekin, p, T = ekin * lam * lam, p * lam, T * lam * lam
         self.step_count += 1
         return {"step": self.step_count, "epot": epot, "ekin": ekin, "etot": epot + ekin, "T": T,

@@ -61,20 +61,37 @@ __global__ __launch_bounds__(256) void k_scale(int N, double* __restrict__ vel, 
     for (int k = 0; k < 3; ++k) vel[(size_t)k * N + i] *= lambda;
 }
 
-// One block: each thread sums a fixed strided subset, then a fixed tree; the
-// result depends only on N.  out = [sum m v^2, sum m v_x, sum m v_y, sum m v_z].
+// Atoms per thread whose loads are issued together in the single-block
+// reductions below (one memory latency per round instead of one per atom).
+constexpr int kBatch = 8;
+
+// One block: each thread sums a fixed strided subset (atoms t, t + 1024, ...
+// in ascending order), then a fixed tree; the result depends only on N.
+// out = [sum m v^2, sum m v_x, sum m v_y, sum m v_z].
 __global__ __launch_bounds__(1024) void k_kinetic(int N, const double* __restrict__ vel,
                                                   const double* __restrict__ mass,
                                                   double* __restrict__ out) {
     __shared__ double sh[4][1024];
     double a[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        const double m = mass[i];
-        const double vx = vel[i], vy = vel[(size_t)N + i], vz = vel[(size_t)2 * N + i];
-        a[0] += m * (vx * vx + vy * vy + vz * vz);
-        a[1] += m * vx;
-        a[2] += m * vy;
-        a[3] += m * vz;
+    for (int i0 = threadIdx.x; i0 < N; i0 += kBatch * blockDim.x) {
+        double m[kBatch], vx[kBatch], vy[kBatch], vz[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int i = i0 + b * blockDim.x;
+            const bool in = i < N;
+            m[b] = in ? mass[i] : 0.0;
+            vx[b] = in ? vel[i] : 0.0;
+            vy[b] = in ? vel[(size_t)N + i] : 0.0;
+            vz[b] = in ? vel[(size_t)2 * N + i] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            if (i0 + b * (int)blockDim.x >= N) break;
+            a[0] += m[b] * (vx[b] * vx[b] + vy[b] * vy[b] + vz[b] * vz[b]);
+            a[1] += m[b] * vx[b];
+            a[2] += m[b] * vy[b];
+            a[3] += m[b] * vz[b];
+        }
     }
     for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = a[k];
     __syncthreads();
@@ -92,13 +109,21 @@ __global__ __launch_bounds__(1024) void k_max_disp(int N, const double* __restri
                                                    double* __restrict__ out) {
     __shared__ double sh[1024];
     double a = 0.0;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        double d2 = 0.0;
-        for (int k = 0; k < 3; ++k) {
-            const double d = pos[(size_t)k * N + i] - ref[(size_t)k * N + i];
-            d2 += d * d;
+    for (int i0 = threadIdx.x; i0 < N; i0 += kBatch * blockDim.x) {
+        double d[kBatch][3];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int i = i0 + b * blockDim.x;
+            const bool in = i < N;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                d[b][k] = in ? pos[(size_t)k * N + i] - ref[(size_t)k * N + i] : 0.0;
         }
-        a = a > d2 ? a : d2;
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const double d2 = d[b][0] * d[b][0] + d[b][1] * d[b][1] + d[b][2] * d[b][2];
+            a = a > d2 ? a : d2;
+        }
     }
     sh[threadIdx.x] = a;
     __syncthreads();

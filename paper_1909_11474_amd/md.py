@@ -16,10 +16,12 @@ only the bond geometry is recomputed (mt_set_update_geometry) until some atom
 has moved skin/2 since the last rebuild (mt_md_max_disp).
 
 Every step runs in the library's kernels; the host keeps only per-step
-scalars (potential energy, kinetic sums, J), read back with one copy per step
-(plus one for the displacement check with a skin).  The library calls' argument
-lists are marshalled once at construction, and the run uses the torch stream
-that is current then.
+scalars (potential energy, kinetic sums, J and the skin's displacement check),
+read back with one copy.  Inside run() without a thermostat the next step's
+first kick, drift and displacement check are issued before that copy, so a
+step waits on the host once instead of twice; the arithmetic and its order
+are unchanged.  The library calls' argument lists are marshalled once at
+construction, and the run uses the torch stream that is current then.
 """
 from __future__ import annotations
 
@@ -71,13 +73,16 @@ class MD:
         m = np.asarray(masses, dtype=np.float64)
         self.mass = torch.as_tensor(m, **kw)
         self.inv_mass = torch.as_tensor(1.0 / m, **kw)
-        # per-step scalars in one buffer: E [1][1], J [1][3], kinetic sums [4]
-        self._sc = torch.empty(8, **kw)
-        self._sc_host = torch.empty(8, dtype=torch.float64, pin_memory=True)
+        # per-step scalars in one buffer: E [1][1], J [1][3], kinetic sums [4],
+        # squared largest displacement since the last list build [1]
+        self._sc = torch.zeros(9, **kw)
+        self._sc_host = torch.empty(9, dtype=torch.float64, pin_memory=True)
         self._sc_np = self._sc_host.numpy()
         self.E = self._sc[0:1].view(1, 1)
         self.J = self._sc[1:4].view(1, 3)
         self.kin = self._sc[4:8]
+        self.disp = self._sc[8:9]
+        self._ahead = False               # next step's first half already issued
         self.F = torch.empty(1, 3, self.N, **kw)
         self.W = torch.empty(1, 1, 6, **kw)
         self.Wi = torch.empty(1, 9, self.N, **kw)
@@ -92,8 +97,6 @@ class MD:
         if self.skin > 0:
             L.check(self._lib.mt_set_list_skin(self.ts._handle, self.skin, self._st), "mt_set_list_skin")
             self.ref = self.pos.clone()
-            self.disp = torch.empty(1, **kw)
-            self._disp_host = torch.empty(1, dtype=torch.float64, pin_memory=True)
         self._marshal()
         self._forces()
 
@@ -122,12 +125,22 @@ class MD:
     def _kick(self):
         L.check(self._lib.mt_md_kick(*self._a_kick), "mt_md_kick")
 
-    def _update_positions(self):
+    def _first_half(self):
+        """Kick, drift and, with a skin, the displacement check (on the GPU)."""
+        self._kick()
+        L.check(self._lib.mt_md_drift(*self._a_drift), "mt_md_drift")
         if self.skin > 0:
             L.check(self._lib.mt_md_max_disp(*self._a_disp), "mt_md_max_disp")
-            with torch.cuda.stream(self._tstream):
-                self._disp_host.copy_(self.disp)             # synchronous
-            if float(self._disp_host[0]) < self._disp_limit:
+
+    def _read_scalars(self):
+        with torch.cuda.stream(self._tstream):
+            self._sc_host.copy_(self._sc)                     # synchronous
+
+    def _update_positions(self):
+        """Bond geometry at the drifted positions; the lists are rebuilt when the
+        displacement read back with the step's scalars reaches skin/2."""
+        if self.skin > 0:
+            if float(self._sc_np[8]) < self._disp_limit:
                 L.check(self._lib.mt_set_update_geometry(*self._a_geometry), "mt_set_update_geometry")
                 return
             with torch.cuda.stream(self._tstream):
@@ -146,17 +159,23 @@ class MD:
         return 2.0 * ekin / (3.0 * self.N * KB_EV)
 
     # -- stepping ------------------------------------------------------------------
-    def step(self) -> dict:
-        lib = self._lib
-        self._kick()
-        L.check(lib.mt_md_drift(*self._a_drift), "mt_md_drift")
+    def step(self, _issue_next: bool = False) -> dict:
+        if not self._ahead:
+            self._first_half()
+            if self.skin > 0:
+                self._read_scalars()                          # the displacement
+        self._ahead = False
         self._update_positions()
         self._forces()
         self._kick()
-        L.check(lib.mt_md_kinetic(*self._a_kinetic), "mt_md_kinetic")
-        # one read-back per step: E, J and the kinetic sums share one buffer
-        with torch.cuda.stream(self._tstream):
-            self._sc_host.copy_(self._sc)                     # synchronous
+        L.check(self._lib.mt_md_kinetic(*self._a_kinetic), "mt_md_kinetic")
+        # without a thermostat the next step's first half needs nothing from
+        # the host: issue it before the read-back (it writes only velocities,
+        # positions and the displacement slot, not E, J or the kinetic sums)
+        if _issue_next and self.thermostat is None:
+            self._first_half()
+            self._ahead = True
+        self._read_scalars()
         sc = self._sc_np
         epot, J, ekin, p = float(sc[0]), sc[1:4].copy(), 0.5 * sc[4] * MV2_TO_EV, sc[5:8].copy()
         T = self.temperature(ekin)
@@ -172,7 +191,7 @@ class MD:
     def run(self, n: int, every: int = 1) -> list:
         out = []
         for k in range(n):
-            rec = self.step()
+            rec = self.step(_issue_next=k + 1 < n)
             if (k + 1) % every == 0:
                 out.append(rec)
         return out

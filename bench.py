@@ -242,12 +242,56 @@ def time_grad(torch, ts, X, steps):
     return t
 
 
+def oracle_sample(call, population, seconds):
+    """Time the CPU oracle on a bounded sample: call(X) on one candidate at a
+    time, in population order and wrapping round, until `seconds` are spent.
+    Returns (candidate evaluations, seconds)."""
+    P = population.shape[0]
+    done = 0
+    c0 = time.perf_counter()
+    while done == 0 or time.perf_counter() - c0 < seconds:
+        k = done % P
+        call(population[k:k + 1])
+        done += 1
+    return done, time.perf_counter() - c0
+
+
+_ORACLE_TOPOLOGY = {}
+
+
+def oracle_rate(args, torch, wl, refs, grad: bool):
+    """The CPU oracle's fitness (or fitness-gradient) rate over a workload's
+    structures, in atom*candidate evals/s, on a third of the CPU budget."""
+    from oracle import tersoff as T
+    s = wl.structs
+    r = {"e": refs[0].cpu().numpy(), "w": refs[1].cpu().numpy(), "f": refs[2].cpu().numpy()}
+    # the oracle's neighbour topology, built once per structure set (setup, not timed)
+    key = (wl.seeds["structures"], s.n_struct, s.n_atoms, wl.R2)
+    t0 = time.perf_counter()
+    if key not in _ORACLE_TOPOLOGY:
+        _ORACLE_TOPOLOGY[key] = T.topology(s, wl.R2)
+    top = _ORACLE_TOPOLOGY[key]
+    t_top = time.perf_counter() - t0
+    fn = T.fitness_grad if grad else T.fitness
+    fn(s, wl.population[:1], r, topology=top)                        # warm-up
+    done, tc = oracle_sample(lambda X: fn(s, X, r, topology=top), wl.population, args.cpu_seconds / 3)
+    what = "fitness and dZ/dx" if grad else "fitness"
+    out = {"value": done * s.n_atoms / tc,
+           "unit": "atom·candidate fitness-grad evals/s" if grad else "atom·candidate evals/s",
+           "cores": int(torch.get_num_threads()), "kind": "oracle",
+           "sample": f"{done} candidate evaluations of the {what} x all {s.n_struct} structures "
+                     f"({s.n_atoms} atoms) in {tc:.1f} s, float64 autograd",
+           "setup_s": {"topology": t_top}}
+    log(f"cpu oracle ({what}, {wl.name.split(':')[0]}): {out['value']:.4e} atom*cand/s")
+    return out
+
+
 def uneven_batching(args, api, torch, W, dev):
     wl = W.config3()
     s = wl.structs
     P = wl.population.shape[0]
     log(f"workload: {wl.name}; atoms {s.n_atoms}, population {P}")
-    ts, _, t_create = make_set(api, torch, wl)
+    ts, refs, t_create = make_set(api, torch, wl)
     st = ts.stats()
     flop_cand, _, _ = set_flops(ts, s.n_atoms)
     X = torch.as_tensor(wl.population, dtype=torch.float64, device=dev).contiguous()
@@ -278,6 +322,8 @@ def uneven_batching(args, api, torch, W, dev):
                         "launches_per_step": P * s.n_struct}
         log(f"uneven plain: {out['plain']['ms_per_step']:.1f} ms/generation")
     ts.close()
+    if not args.no_cpu_baseline:
+        out["cpu_oracle"] = oracle_rate(args, torch, wl, refs, grad=False)
     return out
 
 
@@ -285,7 +331,7 @@ def uneven_gradient(args, api, torch, W, dev):
     wl = W.config4()
     s = wl.structs
     P = wl.population.shape[0]
-    ts, _, _ = make_set(api, torch, wl)
+    ts, refs, _ = make_set(api, torch, wl)
     X = torch.as_tensor(wl.population, dtype=torch.float64, device=dev).contiguous()
     if not args.no_tune:
         ts.autotune(P, "fp32", args.tune_cache)
@@ -296,6 +342,8 @@ def uneven_gradient(args, api, torch, W, dev):
            "steps": args.uneven_grad_steps, "population": P, "seeds": wl.seeds}
     log(f"uneven gradient: {out['ms_per_step']:.3f} ms/call, {out['value']:.4e} atom*cand/s")
     ts.close()
+    if not args.no_cpu_baseline:
+        out["cpu_oracle"] = oracle_rate(args, torch, wl, refs, grad=True)
     return out
 
 
@@ -563,14 +611,7 @@ def main():
         top = T.topology(s, wl.R2)
         T.fitness(s, wl.population[:1], refs, topology=top)           # warm-up
         def sample(seconds):
-            # candidates in population order, wrapping round, until the budget is spent
-            done = 0
-            c0 = time.perf_counter()
-            while done == 0 or time.perf_counter() - c0 < seconds:
-                k = done % P
-                T.fitness(s, wl.population[k:k + 1], refs, topology=top)
-                done += 1
-            return done, time.perf_counter() - c0
+            return oracle_sample(lambda X: T.fitness(s, X, refs, topology=top), wl.population, seconds)
 
         done, tc = sample(args.cpu_seconds)
         cpu = {"value": done * s.n_atoms / tc, "unit": "atom·candidate evals/s",
@@ -597,6 +638,9 @@ def main():
         workloads["uneven_batching"] = uneven_batching(args, api, torch, W, dev)
     if args.uneven_grad_steps > 0:
         workloads["uneven_gradient"] = uneven_gradient(args, api, torch, W, dev)
+    if cpu is not None:
+        # the oracle on the uneven structures too (fitness, and fitness with its gradient)
+        cpu["workloads"] = {k: v["cpu_oracle"] for k, v in workloads.items() if "cpu_oracle" in v}
     if args.md_steps > 0:
         workloads["force_call_64k"] = force_call(args, api, torch, W, dev)
     if args.ga_generations > 0:

@@ -44,3 +44,28 @@ def test_traffic_is_tied_to_the_measured_sources(tmp_path):
     assert t is None or abs(t - (b.PMC_TRAFFIC["fetch_bytes"] + b.PMC_TRAFFIC["write_bytes"])) < 1
     b.PMC_TRAFFIC = dict(b.PMC_TRAFFIC, sha256_16="0" * 16)
     assert b.measured_traffic() is None
+
+
+def test_cpu_oracle_legs_on_a_small_set():
+    """The CPU-oracle legs time the oracle's fitness and its gradient on a
+    bounded sample; the neighbour topology is built once per structure set and
+    reported as setup."""
+    import argparse
+
+    import torch
+
+    import workloads as W
+    from oracle import tersoff as T
+
+    b = load_bench()
+    wl = W.config2(n_struct=3, pop=4)
+    r = T.reference_data(wl.structs, wl.hidden_x, wl.R1, wl.R2)
+    refs = tuple(torch.as_tensor(r[k]) for k in ("e", "w", "f"))
+    args = argparse.Namespace(cpu_seconds=0.3)
+    fit = b.oracle_rate(args, torch, wl, refs, grad=False)
+    grad = b.oracle_rate(args, torch, wl, refs, grad=True)
+    for leg in (fit, grad):
+        assert leg["kind"] == "oracle" and leg["value"] > 0 and leg["cores"] >= 1
+    assert grad["unit"].endswith("fitness-grad evals/s")
+    assert grad["setup_s"]["topology"] < fit["setup_s"]["topology"] + 1e-3
+    assert len(b._ORACLE_TOPOLOGY) == 1

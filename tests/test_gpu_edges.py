@@ -126,3 +126,44 @@ def test_population_extremes_give_identical_candidates(api):
             assert np.array_equal(Z1[0], Zbig[c])
             assert np.array_equal(Zbig[c], Zbig[c + 8 * 124])
     ts.close()
+
+
+def bcc_cell(g, reps, d=2.6, sigma=0.05):
+    """Displaced BCC Si of reps^3 cubic cells with nearest-neighbour distance d:
+    8 neighbours at d and 6 at 2d/sqrt(3) (3.0 A for d = 2.6, inside the
+    switching zone R1 < r < R2), 14 in all, 13-14 after the displacements."""
+    a = 2.0 * d / np.sqrt(3.0)
+    grid = np.array([[i, j, k] for i in range(reps) for j in range(reps) for k in range(reps)],
+                    dtype=np.float64)
+    frac = (grid[:, None, :] + np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5]])[None]).reshape(-1, 3)
+    return W.displace(g, frac * a, sigma), np.eye(3) * reps * a
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_coordination_above_twelve(api, precision):
+    """BCC cells of 16 (cell width below 2 R2: several images), 54 and 128
+    atoms run the kernels of the largest coordination class beside diamond
+    cells in the smallest: energies, forces, virials and fitness against the
+    oracle, batched = plain in float64.  The adjoint is compiled up to 12
+    neighbours, so fitness_grad rejects the set with MT_EINVAL."""
+    g = rng(41)
+    s = W.make_set([bcc_cell(g, r) for r in (2, 3, 4)] + W.strained_diamond_cells(42, 2))
+    ts = api.from_structures(s)
+    st = ts.stats()
+    assert st["max_coordination"] == 14 and st["n_large"] == 0
+    X = W.draw_params(rng(43), 3)
+    check_eval(ts, s, X, precision)
+    refs = T.reference_data(s, W.draw_params(rng(44), 1)[0], R1, R2)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    Zb = ts.fitness(X, precision=precision).cpu().numpy()
+    Zp = ts.fitness(X, precision=precision, schedule="plain").cpu().numpy()
+    Zo = T.fitness(s, X, refs, topology=T.topology(s, R2))
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    assert np.abs(Zb - Zo).max() <= tol * np.abs(Zo).max()
+    if precision == "fp64":
+        assert np.array_equal(Zb, Zp)
+    from paper_1909_11474_amd import _lib as L
+    with pytest.raises(L.MTError) as e:
+        ts.fitness_grad(X, precision=precision)
+    assert e.value.code == L.MT_EINVAL
+    ts.close()

@@ -144,8 +144,9 @@ def test_coordination_above_twelve(api, precision):
     """BCC cells of 16 (cell width below 2 R2: several images), 54 and 128
     atoms run the kernels of the largest coordination class beside diamond
     cells in the smallest: energies, forces, virials and fitness against the
-    oracle, batched = plain in float64.  The adjoint is compiled up to 12
-    neighbours, so fitness_grad rejects the set with MT_EINVAL."""
+    oracle, batched = plain in float64, and the Tersoff form's E, F, W, W_i.
+    The adjoint is compiled up to 12 neighbours, so fitness_grad rejects the
+    set with MT_EINVAL in both forms."""
     g = rng(41)
     s = W.make_set([bcc_cell(g, r) for r in (2, 3, 4)] + W.strained_diamond_cells(42, 2))
     ts = api.from_structures(s)
@@ -162,8 +163,12 @@ def test_coordination_above_twelve(api, precision):
     assert np.abs(Zb - Zo).max() <= tol * np.abs(Zo).max()
     if precision == "fp64":
         assert np.array_equal(Zb, Zp)
+    # the nine-parameter Tersoff form through the same coordination class
+    Xf = W.draw_params_full(rng(45), 2)
+    check_eval(ts, s, Xf, precision)
     from paper_1909_11474_amd import _lib as L
-    with pytest.raises(L.MTError) as e:
-        ts.fitness_grad(X, precision=precision)
-    assert e.value.code == L.MT_EINVAL
+    for Xg in (X, Xf):
+        with pytest.raises(L.MTError) as e:
+            ts.fitness_grad(Xg, precision=precision)
+        assert e.value.code == L.MT_EINVAL
     ts.close()

@@ -172,3 +172,35 @@ def test_coordination_above_twelve(api, precision):
             ts.fitness_grad(Xg, precision=precision)
         assert e.value.code == L.MT_EINVAL
     ts.close()
+
+
+def shell16(radii=(2.6, 3.0)):
+    """One atom with exactly 16 neighbours (the neighbour cap): 16 atoms on a
+    Fibonacci sphere around it, alternately at 2.6 A and at 3.0 A (inside the
+    switching zone), at least 2.1 A apart."""
+    n = 16
+    k = np.arange(n) + 0.5
+    phi = np.arccos(1.0 - 2.0 * k / n)
+    th = np.pi * (1.0 + 5.0 ** 0.5) * k
+    u = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], axis=1)
+    r = np.where(np.arange(n) % 2 == 0, radii[0], radii[1])[:, None]
+    c = np.array([10.0, 10.0, 10.0])
+    return np.vstack([c, c + r * u]), BOX
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_atom_at_the_neighbour_cap(api, precision):
+    """An atom with MT_MAX_NBR = 16 neighbours (the largest compiled bond
+    count) beside a diamond cell: E, F, W, W_i vs oracle for both forms; one
+    fewer slot than the atom needs is MT_ENBR_OVERFLOW."""
+    pos, cell = shell16()
+    s = W.make_set([(pos, cell), W.diamond(1, 1, 1)])
+    ts = api.from_structures(s)
+    assert ts.stats()["max_coordination"] == 16
+    check_eval(ts, s, W.draw_params(rng(46), 3), precision)
+    check_eval(ts, s, W.draw_params_full(rng(47), 2), precision)
+    ts.close()
+    from paper_1909_11474_amd import _lib as L
+    with pytest.raises(L.MTError) as e:
+        api.TersoffSet(pos, cell[None], [0, len(pos)], max_nbr=15)
+    assert e.value.code == L.MT_ENBR_OVERFLOW

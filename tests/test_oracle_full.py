@@ -62,6 +62,30 @@ def test_equilateral_trimer_closed_form():
         assert abs(energy(pos, cell, x) - ref) <= 1e-13 * 3 * (fr + b * fa)
 
 
+def test_trimer_with_a_switching_zone_bond_closed_form():
+    """Isosceles trimer, apex bonds s <= R1 and base c in (R1, R2), with g^T:
+    zeta of an apex bond from the apex carries f_C(s) = 1, of an apex bond from a
+    base atom f_C(c), of the base bond f_C(s) (Sec. II.A Eqs. 2-9)."""
+    for x in W.draw_params_full(rng(27), 3):
+        D0, alpha, r0, S, gamma, n, cc, d, h = x
+        s, c = 2.4, 2.95
+
+        def g(cos):
+            return gamma * (1 + cc * cc / (d * d) - cc * cc / (d * d + (cos - h) ** 2))
+
+        def bond(r, zeta):
+            b = (1 + zeta ** n) ** (-1 / (2 * n))
+            fr = D0 / (S - 1) * math.exp(-math.sqrt(2 * S) * alpha * (r - r0))
+            fa = S * D0 / (S - 1) * math.exp(-math.sqrt(2 / S) * alpha * (r - r0))
+            return fc(r) * (fr - b * fa)
+
+        cos0, cos1 = 1 - c * c / (2 * s * s), c / (2 * s)
+        ref = bond(s, fc(s) * g(cos0)) + bond(s, fc(c) * g(cos1)) + bond(c, fc(s) * g(cos1))
+        y = math.sqrt(s * s - c * c / 4)
+        pos, cell = _isolated([[0, y, 0], [-c / 2, 0, 0], [c / 2, 0, 0]])
+        assert abs(energy(pos, cell, x) - ref) <= 1e-13 * max(1.0, abs(ref))
+
+
 def test_angular_function_approaches_the_minimal_one():
     """Sec. II.B: for c^2/d^2 >> 1, d^2 >> 1 and gamma << 1, g^T approaches
     beta (cos - h)^2 with beta = gamma c^2 / d^4.  With S = 2 and c = 10 d^3

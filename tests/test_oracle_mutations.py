@@ -19,8 +19,9 @@ R1, R2 = 2.8, 3.2
 
 def _pins_hold() -> bool:
     x = W.TABLE2_X
-    # perfect diamond closed form at two lattice constants
-    for a in (5.3, 5.43):
+    # perfect diamond closed form at two lattice constants, and at one whose
+    # bonds lie in the switching zone (f_C of the third atom inside zeta)
+    for a in (5.3, 5.43, 6.8):
         pos, cell = W.diamond(1, 1, 1, a)
         e = T.evaluate(pos, cell, x, R1, R2)["E"][0] / 8
         if abs(e - T.diamond_closed_form(x, a)) > 1e-12:
@@ -49,6 +50,11 @@ def _pins_hold() -> bool:
     ref = 3 * D0 * (e1 * e1 - 2 * b * e1)
     if abs(T.evaluate(pos, np.eye(3) * 40, x, R1, R2)["E"][0] - ref) > 1e-12:
         return False
+    # isosceles trimer with its base bond in the switching zone
+    from test_oracle_pins import _isosceles_trimer_energy, isosceles_trimer
+    pos, cell = isosceles_trimer(2.4, 2.95)
+    if abs(T.evaluate(pos, cell, x, R1, R2)["E"][0] - _isosceles_trimer_energy(x, 2.4, 2.95)) > 1e-12:
+        return False
     return True
 
 
@@ -70,7 +76,12 @@ def _site_energies_variant(kind):
         cos = (d[pt] * d[qt]).sum(dim=1) / (r[pt] * r[qt])
         hh = -h if kind == "h_sign" else h
         g = beta * (cos - hh) ** 2
-        fcq = torch.ones_like(fc[qt]) if kind == "no_fc_in_zeta" else fc[qt]
+        if kind == "no_fc_in_zeta":
+            fcq = torch.ones_like(fc[qt])
+        elif kind == "fc_ij_in_zeta":
+            fcq = fc[pt]                      # the bond's own cutoff instead of the third atom's
+        else:
+            fcq = fc[qt]
         zeta = torch.zeros_like(r).index_add(0, pt, fcq * g)
         pos = zeta > 0
         zs = torch.where(pos, zeta, torch.ones_like(zeta))
@@ -83,7 +94,7 @@ def _site_energies_variant(kind):
     return orig, variant
 
 
-@pytest.mark.parametrize("kind", ["h_sign", "b_exponent", "no_half"])
+@pytest.mark.parametrize("kind", ["h_sign", "b_exponent", "no_half", "no_fc_in_zeta", "fc_ij_in_zeta"])
 def test_planted_energy_mistakes_are_caught(monkeypatch, kind):
     _, variant = _site_energies_variant(kind)
     monkeypatch.setattr(T, "site_energies", variant)

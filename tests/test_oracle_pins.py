@@ -44,9 +44,12 @@ def test_table2_fixture_matches_workload_constants(golden):
 # Closed forms and printed values
 # ----------------------------------------------------------------------------
 
-@pytest.mark.parametrize("a", [5.25, 5.43, 5.60])
+@pytest.mark.parametrize("a", [5.25, 5.43, 5.60, 6.8])
 def test_diamond_lattice_closed_form(a):
-    """Perfect diamond: four neighbours at sqrt(3)a/4 with cos(theta) = -1/3."""
+    """Perfect diamond: four neighbours at sqrt(3)a/4 with cos(theta) = -1/3.
+    At a = 6.8 A the bonds (2.94 A) lie in the switching zone (R1, R2) and the
+    second shell (4.81 A) beyond R2, so zeta = 3 f_C(r) beta (-1/3 - h)^2 carries
+    the cutoff factor of the third atom (Sec. II.A Eqs. 7 and 9)."""
     xs = [W.TABLE2_X] + list(W.draw_params(rng(11), 4))
     pos, cell = W.diamond(2, 2, 2, a)
     for x in xs:
@@ -191,6 +194,52 @@ def test_equilateral_trimer_closed_form():
     x = W.TABLE2_X
     pos, cell = _isolated([[0, 0, 0], [2.3, 0, 0], [1.15, 2.3 * math.sqrt(3) / 2, 0]])
     assert abs(energy(pos, cell, x) - (-4.208640959670)) < 1e-11
+
+
+def _isosceles_trimer_energy(x, s, c):
+    """Isosceles trimer by hand: apex atom 0 with two bonds of length s <= R1,
+    base atoms 1 and 2 at distance c in the switching zone.  Directed bonds
+    (Sec. II.A Eqs. 2-7, Sec. II.B Eq. 10):
+      0->1, 0->2: r = s, partner bond of length s at the apex angle,
+                  zeta = f_C(s) beta (cos0 - h)^2, cos0 = 1 - c^2 / (2 s^2);
+      1->0, 2->0: r = s, partner bond of length c at the base angle,
+                  zeta = f_C(c) beta (cos1 - h)^2, cos1 = c / (2 s);
+      1->2, 2->1: r = c, partner bond of length s at the base angle,
+                  zeta = f_C(s) beta (cos1 - h)^2;
+    E = 1/2 sum over the six directed bonds of f_C(r) [f_R(r) - b f_A(r)]."""
+    D0, alpha, r0, beta, n, h = x
+
+    def fcut(r):
+        return 1.0 if r <= R1 else (0.0 if r >= R2 else
+                                    0.5 * (1 + math.cos(math.pi * (r - R1) / (R2 - R1))))
+
+    def bond(r, zeta):
+        b = (1 + zeta ** n) ** (-1 / (2 * n)) if zeta > 0 else 1.0
+        e1 = math.exp(-alpha * (r - r0))
+        return fcut(r) * D0 * (e1 * e1 - 2 * b * e1)
+
+    cos0 = 1 - c * c / (2 * s * s)
+    cos1 = c / (2 * s)
+    g0 = beta * (cos0 - h) ** 2
+    g1 = beta * (cos1 - h) ** 2
+    return 0.5 * (2 * bond(s, fcut(s) * g0) + 2 * bond(s, fcut(c) * g1) + 2 * bond(c, fcut(s) * g1))
+
+
+def isosceles_trimer(s, c):
+    y = math.sqrt(s * s - c * c / 4)
+    return _isolated([[0, y, 0], [-c / 2, 0, 0], [c / 2, 0, 0]])
+
+
+def test_trimer_with_a_switching_zone_bond_closed_form():
+    """A bond in (R1, R2) enters zeta of the other bonds through f_C of the third
+    atom (Sec. II.A Eq. 7): the apex bonds see the base bond's cutoff, the base
+    bond sees the apex bonds' (full) cutoff."""
+    for x in [W.TABLE2_X] + list(W.draw_params(rng(17), 3)):
+        for s, c in ((2.4, 2.95), (2.3, 3.1)):
+            assert R1 < c < R2 and s <= R1
+            pos, cell = isosceles_trimer(s, c)
+            ref = _isosceles_trimer_energy(x, s, c)
+            assert abs(energy(pos, cell, x) - ref) <= 1e-13 * max(1.0, abs(ref))
 
 
 def test_beta_zero_reduces_to_pair_potential():

@@ -248,6 +248,29 @@ int fitness_grad_tf(mt_set* set, const double* x, int P, const double* w, int pr
                     double* Z, double* dZdx, void* stream);
 
 /*
+ * Per-structure terms behind the most recent fitness_eval, fitness_eval_tf,
+ * fitness_grad or fitness_grad_tf call on this set: the predicted quantities
+ * whose residuals the Sec. III.B fitness sums, for comparing predicted and
+ * reference energies and virials structure by structure.  They are read from
+ * the partial sums that call left in the set's workspace, so they are the
+ * values its Z was computed from (float32 arithmetic with float64 sums for
+ * MT_FP32_ACC64).
+ *   x   device [P][6] or [P][9]: the parameter sets of that call; read only to
+ *       give candidates outside the potential's domain NaN rows
+ *   e   device [P][S]     E_s / N_s (eV/atom), or NULL
+ *   w   device [P][S][6]  W_s / N_s (eV/atom), xx yy zz yz zx xy, or NULL
+ *   rf  device [P][S]     sum over the structure's atoms of |F_i - F*_i|^2
+ *                         (eV^2/A^2), or NULL
+ * Enqueued on `stream`, which must be that call's stream or ordered after it.
+ * Errors: MT_EINVAL for a NULL set or x, or P other than that call's;
+ * MT_ESTATE when no fitness call has run since the set was created, or
+ * tersoff_eval, mt_profile_fitness_kernels, mt_autotune, a position update or
+ * a reference attachment has overwritten or outdated the partial sums since.
+ */
+int fitness_terms(mt_set* set, const double* x, int P, double* e, double* w, double* rf,
+                  void* stream);
+
+/*
  * Molecular-dynamics steps for the potential's application (Sec. IV.C:
  * equilibrium and homogeneous non-equilibrium MD of diamond Si).  Velocity
  * Verlet is kick(dt/2), drift(dt), mt_set_update_positions, tersoff_eval,

@@ -170,10 +170,12 @@ def _forward(top: _Topology, x: torch.Tensor, R1: float, R2: float, create_graph
 
 
 def evaluate_set(structs, x, R1: float, R2: float, atom_virial: bool = False,
-                 velocities: Optional[np.ndarray] = None):
+                 velocities: Optional[np.ndarray] = None, topology: Optional["_Topology"] = None):
     """Energy [S], forces [N,3], virial [S,6] (xx yy zz yz zx xy), site energies [N];
-    optionally per-atom virial [N,3,3] and heat current [3].  All eV / A units."""
-    top = _Topology(structs, R2)
+    optionally per-atom virial [N,3,3] and heat current [3].  All eV / A units.
+    ``topology`` (from ``topology(structs, R2)``) reuses the neighbour entries
+    of earlier calls on the same structures."""
+    top = topology or _Topology(structs, R2)
     xt = _as_x(x)
     E, F, W6, U = _forward(top, xt, R1, R2, create_graph=False)
     out = {"E": E.detach().numpy(), "F": F.detach().numpy(), "W6": W6.detach().numpy(),

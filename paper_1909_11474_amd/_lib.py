@@ -54,6 +54,7 @@ SIGNATURES = {
     "fitness_eval_tf": (_i, [_vp, _vp, _i, ctypes.POINTER(_d), _i, _i, _vp, _vp]),
     "fitness_grad": (_i, [_vp, _vp, _i, ctypes.POINTER(_d), _i, _vp, _vp, _vp]),
     "fitness_grad_tf": (_i, [_vp, _vp, _i, ctypes.POINTER(_d), _i, _vp, _vp, _vp]),
+    "fitness_terms": (_i, [_vp, _vp, _i, _vp, _vp, _vp, _vp]),
     "mt_autotune": (_i, [_vp, _i, _i, ctypes.c_char_p]),
     "mt_profile_enable": (_i, [_vp, _i]),
     "mt_profile_read": (_i, [_vp, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_int64)]),

@@ -219,6 +219,22 @@ class TersoffSet:
         L.check(rc, name)
         return Z, G
 
+    def fitness_terms(self, x):
+        """Per-structure terms of the last fitness call on this set with the
+        parameter sets x (its P and form): dict of device float64 tensors
+        e [P, S] (eV/atom), w [P, S, 6] (eV/atom) and rf [P, S] (squared force
+        residual, eV^2/A^2)."""
+        xt = self._x(x)
+        P = xt.shape[0]
+        with torch.cuda.device(self.device):
+            e = torch.empty(P, self.S, dtype=torch.float64, device=self.device)
+            w = torch.empty(P, self.S, 6, dtype=torch.float64, device=self.device)
+            rf = torch.empty(P, self.S, dtype=torch.float64, device=self.device)
+            rc = self._lib.fitness_terms(self._handle, _ptr(xt), P, _ptr(e), _ptr(w), _ptr(rf),
+                                         self._stream())
+        L.check(rc, "fitness_terms")
+        return {"e": e, "w": w, "rf": rf}
+
     def profile(self, enable: bool = True):
         """Bracket each batched / adjoint kernel launch with HIP events."""
         L.check(self._lib.mt_profile_enable(self._handle, 1 if enable else 0), "mt_profile_enable")

@@ -68,7 +68,7 @@ mt::SetDev mt_set::dev() const {
     return d;
 }
 
-static void clear_graphs(mt_set* set) {
+void mt::clear_graphs(mt_set* set) {
     for (auto& g : set->graphs) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
         if (g.graph) (void)hipGraphDestroy(g.graph);
@@ -180,6 +180,7 @@ int mt_set_attach_reference(mt_set* set, const double* e_ref, const double* w_re
     if (!e_ref || !w_ref || !f_ref) return fail(MT_EINVAL, "reference pointers must not be NULL");
     if (!set->usable) return fail(MT_ESTATE, "the set's last position update failed; destroy it");
     clear_graphs(set);
+    set->fit_P = 0;
     return attach_reference(set, e_ref, w_ref, f_ref, (hipStream_t)stream);
 }
 
@@ -192,6 +193,7 @@ int mt_set_update_positions(mt_set* set, const double* pos, void* stream) {
     std::vector<int64_t> off(set->h_off.begin(), set->h_off.end());
     const auto layout = std::make_tuple(set->h_kmax, set->h_xsize, set->h_npad, set->h_large, set->nslots);
     set->has_ref = false;
+    set->fit_P = 0;
     const int rc = build_set(set, off.data(), pos, set->cell.as<double>(), (hipStream_t)stream);
     if (rc != MT_OK) {
         set->usable = false;
@@ -257,6 +259,7 @@ static int eval_impl(mt_set* set, const double* x, int form, int P, int precisio
     if (heat_current && !vel) return fail(MT_EINVAL, "heat_current needs vel");
     hipStream_t st = (hipStream_t)stream;
     TRY(ensure_workspace(set, P, kNVEval));
+    set->fit_P = 0;
     set->cur_x = x;
     set->cur_form = form;
     if (schedule == MT_BATCHED) {
@@ -292,6 +295,9 @@ static int check_fitness(mt_set* set, const double* x, int P, const double* w, i
     return MT_OK;
 }
 
+static int fitness_graph(mt_set* set, const double* x, int form, int P, const double* w,
+                         int precision, int schedule, double* Z, hipStream_t st);
+
 static int fitness_impl(mt_set* set, const double* x, int form, int P, const double* w,
                         int precision, int schedule, double* Z, void* stream) {
     TRY(check_fitness(set, x, P, w, precision, Z));
@@ -299,11 +305,23 @@ static int fitness_impl(mt_set* set, const double* x, int form, int P, const dou
         return fail(MT_EINVAL, "schedule must be MT_BATCHED or MT_PLAIN");
     hipStream_t st = (hipStream_t)stream;
     TRY(ensure_workspace(set, P, kNVFit));
+    set->fit_P = 0;
     const LaunchCfg cfg = cfg_for(set, P, precision);
     if (schedule == MT_PLAIN || set->profiling || !cfg.graph)
-        return fitness_sequence(set, x, form, P, w, precision, schedule, Z, st);
+        TRY(fitness_sequence(set, x, form, P, w, precision, schedule, Z, st));
+    else
+        TRY(fitness_graph(set, x, form, P, w, precision, schedule, Z, st));
+    set->fit_P = P;
+    set->fit_form = form;
+    return MT_OK;
+}
 
-    // Batched: replay a captured graph of the batched kernel(s) and finalize.
+// Batched fitness by replaying a captured graph of the batched kernel(s) and
+// the finalize (captured on the first call with these arguments).
+static int fitness_graph(mt_set* set, const double* x, int form, int P, const double* w,
+                         int precision, int schedule, double* Z, hipStream_t st) {
+    const LaunchCfg cfg = cfg_for(set, P, precision);
+
     GraphKey key;
     key.x = x; key.Z = Z; key.P = P; key.precision = precision; key.form = form;
     key.block = cfg.block; key.tile = cfg.tile; key.persistent = cfg.persistent;
@@ -389,7 +407,10 @@ static int grad_impl(mt_set* set, const double* x, int form, int P, const double
                                    std::to_string(MT_MAX_GRAD_NBR));
     hipStream_t st = (hipStream_t)stream;
     TRY(ensure_workspace(set, P, kNVFit));
+    set->fit_P = 0;
     TRY(fitness_sequence(set, x, form, P, w, precision, MT_BATCHED, Z, st));
+    set->fit_P = P;
+    set->fit_form = form;
     const LaunchCfg cfg = cfg_for(set, P, precision);
     TRY(launch_adjoint(set, cfg, P, precision, w, Z, st));
     return launch_finalize_grad(set, P, Z, dZdx, st);
@@ -407,6 +428,20 @@ int fitness_grad_tf(mt_set* set, const double* x, int P, const double* w, int pr
     return grad_impl(set, x, 1, P, w, precision, Z, dZdx, stream);
 }
 
+int fitness_terms(mt_set* set, const double* x, int P, double* e, double* w, double* rf,
+                  void* stream) {
+    if (!set) return fail(MT_EINVAL, "set is NULL");
+    if (!x) return fail(MT_EINVAL, "x is NULL");
+    if (P <= 0) return fail(MT_EINVAL, "P must be positive");
+    if (set->fit_P == 0)
+        return fail(MT_ESTATE, "no fitness partial sums: call fitness_eval or fitness_grad first");
+    if (P != set->fit_P)
+        return fail(MT_EINVAL, "P differs from the last fitness call's (" + std::to_string(set->fit_P) + ")");
+    set->cur_x = x;
+    set->cur_form = set->fit_form;
+    return launch_fitness_terms(set, P, e, w, rf, (hipStream_t)stream);
+}
+
 int mt_profile_enable(mt_set* set, int enable) {
     if (!set) return fail(MT_EINVAL, "set is NULL");
     set->profiling = enable != 0;
@@ -421,6 +456,7 @@ int mt_profile_fitness_kernels(mt_set* set, const double* x, int nx, int P, int 
     if (!ms || !launches) return fail(MT_EINVAL, "ms and launches must not be NULL");
     if (!set->has_ref) return fail(MT_ENOREF, "no reference data attached to the set");
     TRY(ensure_workspace(set, P, kNVFit));
+    set->fit_P = 0;
     set->cur_x = x;
     set->cur_form = nx == 9 ? 1 : 0;
     return time_batched_kernels(set, cfg_for(set, P, precision), P, precision, reps,
@@ -504,6 +540,7 @@ int mt_autotune(mt_set* set, int P, int precision, const char* cache_path) {
     }
     int rc = ensure_workspace(set, P, kNVFit);
     if (rc) { (void)hipStreamDestroy(st); return rc; }
+    set->fit_P = 0;
     set->cur_x = xb.as<double>();
     set->cur_form = 0;
     hipEvent_t e0, e1;

@@ -41,7 +41,7 @@ constexpr int kNVFit = 8;          // partial sums per slot: E, W6, |F - F*|^2
 constexpr int kNVEval = 16;        // E, W6, |F-F*|^2, J3, unused
 constexpr int kNVGrad = 8;         // dZ/dx (6), unused (2)
 constexpr int kNVGradTF = 16;      // Tersoff form: dZ/dx (9), unused (7)
-constexpr int kNParam = 24;        // per-candidate decoded parameter record
+constexpr int kNParam = 26;        // per-candidate decoded parameter record (25 used)
 
 // Decoded parameter record (float or double), filled per work item in LDS.
 // Both potential forms share it: f_R = DR e^{-lambda (r - r0)},
@@ -77,7 +77,8 @@ enum ParamIndex {
     P_GAM = 20,     // gamma
     P_K = 21,       // gamma c^2 / d^2
     P_D2 = 22,      // d^2
-    P_KD2 = 23      // K d^2
+    P_KD2 = 23,     // K d^2
+    P_HLO = 24      // h - float(h) (float records; zero in double records)
 };
 
 struct Item {       // one (structure, candidate range) work item of the batched kernel
@@ -124,12 +125,12 @@ __device__ __forceinline__ double dexp2(double x) { return exp2(x); }
 __device__ __forceinline__ double dlog2(double x) { return log2(x); }
 __device__ __forceinline__ double drcp(double x) { return 1.0 / x; }
 
-// float64 2^y and log2(x) for the energy terms of the float path: about 1e-12
-// relative error, finite normal arguments only.
-//   2^y: y = k + f with k = rint(y), |f| <= 1/2; 2^f = e^(f ln 2) by its Taylor
-//   series to degree 9 (remainder (ln2/2)^10 / 10! < 7e-12).
-//   log2(x): x = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s),
-//   s = (m - 1)/(m + 1), |s| <= 0.172, series to s^13 (remainder < 2e-12).
+
+
+// float64 2^y for the energy terms of the float path: about 1e-12 relative
+// error, finite arguments only.  y = k + f with k = rint(y), |f| <= 1/2;
+// 2^f = e^(f ln 2) by its Taylor series to degree 9 (remainder
+// (ln2/2)^10 / 10! < 7e-12).
 __device__ __forceinline__ double exp2_acc(double y) {
     const double k = __builtin_rint(y);
     const double f = y - k;
@@ -144,29 +145,6 @@ __device__ __forceinline__ double exp2_acc(double y) {
     p = p * f + 0.6931471805599453;
     p = p * f + 1.0;
     return __builtin_amdgcn_ldexp(p, (int)k);
-}
-
-__device__ __forceinline__ double log2_acc(double x) {
-    double m = __builtin_amdgcn_frexp_mant(x);      // [1/2, 1)
-    int e = __builtin_amdgcn_frexp_exp(x);
-    if (m < 0.70710678118654752) {
-        m *= 2.0;
-        e -= 1;
-    }
-    const double a = m + 1.0;
-    double q = __builtin_amdgcn_rcp(a);             // refined twice: error ~ (2^-26)^4
-    q = q * (2.0 - a * q);
-    q = q * (2.0 - a * q);
-    const double s = (m - 1.0) * q;
-    const double s2 = s * s;
-    double t = 1.0 / 13.0;                          // 1/(2i+1), i = 6 .. 0
-    t = t * s2 + 1.0 / 11.0;
-    t = t * s2 + 1.0 / 9.0;
-    t = t * s2 + 1.0 / 7.0;
-    t = t * s2 + 1.0 / 5.0;
-    t = t * s2 + 1.0 / 3.0;
-    t = t * s2 + 1.0;
-    return (double)e + (2.0 * s * t) * 1.4426950408889634;     // ln m / ln 2
 }
 
 template <typename S>

@@ -314,6 +314,27 @@ __global__ __launch_bounds__(256) void k_finalize_grad(FinArgs F, double* dZdx) 
     }
 }
 
+// Per-structure terms of the fitness partial sums: e_s = E_s / N_s,
+// w_s = W_s / N_s and the squared force residual of the structure; NaN rows
+// for candidates outside the potential's domain.
+__global__ __launch_bounds__(256) void k_fitness_terms(FinArgs F, double* e_out, double* w_out,
+                                                       double* rf_out) {
+    const int c = blockIdx.x;
+    const SetDev& d = F.set;
+    const bool ok = cand_valid(F.x, c, F.full);
+    const double nan = __longlong_as_double(0x7ff8000000000000ll);
+    for (int s = threadIdx.x; s < d.S; s += blockDim.x) {
+        double e, w6[6], rf, j3[3];
+        struct_sums(F, c, s, &e, w6, &rf, j3);
+        const double n = (double)(d.st_off[s + 1] - d.st_off[s]);
+        const size_t o = (size_t)c * d.S + s;
+        if (e_out) e_out[o] = ok ? e / n : nan;
+        if (w_out)
+            for (int k = 0; k < 6; ++k) w_out[6 * o + k] = ok ? w6[k] / n : nan;
+        if (rf_out) rf_out[o] = ok ? rf : nan;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_finalize_eval(FinArgs F) {
     __shared__ double sh[11][256];
     const int c = blockIdx.x;
@@ -783,7 +804,11 @@ int reserve_twopass(mt_set* set, const ItemPlan* plan, int P, int precision) {
         if (set->h_large[s]) add(s);
     if (plan)
         for (int s : plan->twopass) add(s);
+    // a captured fitness graph holds the buffer's address in its two-pass
+    // launches: growing the buffer frees that memory, so those graphs go too
+    const void* before = set->gbuf.p;
     if (need) HIPCHECK(set->gbuf.reserve(need));
+    if (set->gbuf.p != before) clear_graphs(set);
     return MT_OK;
 }
 
@@ -872,6 +897,13 @@ int launch_finalize_eval(mt_set* set, int P, double* energy, double* virial, dou
     F.virial = virial;
     F.heat = heat;
     hipLaunchKernelGGL(k_finalize_eval, dim3(P), dim3(256), 0, st, F);
+    HIPCHECK(hipGetLastError());
+    return MT_OK;
+}
+
+int launch_fitness_terms(mt_set* set, int P, double* e, double* w, double* rf, hipStream_t st) {
+    FinArgs F = make_fin(set, kNVFit, set->partial.as<double>());
+    hipLaunchKernelGGL(k_fitness_terms, dim3(P), dim3(256), 0, st, F, e, w, rf);
     HIPCHECK(hipGetLastError());
     return MT_OK;
 }

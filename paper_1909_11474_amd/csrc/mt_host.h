@@ -130,6 +130,10 @@ struct mt_set {
     // the Tersoff form) and their form (0 minimal, 1 Tersoff form)
     const double* cur_x = nullptr;
     int cur_form = 0;
+    // population size and form of the fitness partial sums the workspace holds
+    // (after fitness_eval / fitness_grad; 0 once another call overwrote them)
+    int fit_P = 0;
+    int fit_form = 0;
 
     // workspaces
     mt::DevBuf partial;                      // [P][nslots][NV] double
@@ -164,6 +168,10 @@ int export_neighbors(const mt_set* set, int32_t* i, int32_t* j, int32_t* shift, 
 // New positions with the neighbour lists of the last build (no host sync).
 int update_geometry(mt_set* set, const double* pos, hipStream_t stream);
 
+// mt_api.hip: destroy the set's captured fitness graphs (after any workspace
+// they reference is reallocated)
+void clear_graphs(mt_set* set);
+
 // mt_eval.hip
 int launch_batched(mt_set* set, const LaunchCfg& cfg, int P, int precision, int mode,
                    const double* vel, double* force, double* atom_virial, hipStream_t stream);
@@ -180,6 +188,10 @@ int reserve_twopass(mt_set* set, const ItemPlan* plan, int P, int precision);
 int launch_finalize_fit(mt_set* set, int P, const double* w, double* Z, hipStream_t stream);
 int launch_finalize_eval(mt_set* set, int P, double* energy, double* virial, double* heat,
                          hipStream_t stream);
+// Per-structure e_s, w_s and squared force residual from the fitness partial
+// sums in the set's workspace (set->cur_x and cur_form select the candidates'
+// domain check).
+int launch_fitness_terms(mt_set* set, int P, double* e, double* w, double* rf, hipStream_t stream);
 int launch_adjoint(mt_set* set, const LaunchCfg& cfg, int P, int precision, const double* w,
                    const double* Z, hipStream_t stream);
 int launch_adjoint_plain(mt_set* set, int P, int precision, const double* w, const double* Z,

@@ -86,7 +86,7 @@ __device__ __forceinline__ void decode_record(const double* __restrict__ x, S* _
         put_split(o, P_DA, P_DALO, Sl * D0 / (Sl - 1.0));
         put_split(o, P_N, P_NLO, n);
         put_split(o, P_NINV2N, P_NINV2NLO, -1.0 / (2.0 * n));
-        o[P_H] = (S)h;
+        put_split(o, P_H, P_HLO, h);
         o[P_VALID] = ok ? S(1) : S(0);
         o[P_HMU] = (S)(0.5 * mu);
         o[P_HLAMBDA] = (S)(0.5 * lam);
@@ -114,7 +114,7 @@ __device__ __forceinline__ void decode_record(const double* __restrict__ x, S* _
         o[P_ZS] = (S)be;
         o[P_N] = (S)n;
         o[P_NINV2N] = (S)(-1.0 / (2.0 * n));
-        o[P_H] = (S)h;
+        put_split(o, P_H, P_HLO, h);
         o[P_VALID] = ok ? S(1) : S(0);
         o[P_HMU] = (S)(0.5 * al);
         o[P_CCS] = (S)(0.5 * be);
@@ -244,7 +244,7 @@ __device__ __forceinline__ void run_batched(const BArgs<S>& A, const Item& it, c
     const S* __restrict__ pbuf = reinterpret_cast<const S*>(lds);
     Vec4<S>* __restrict__ xb = reinterpret_cast<Vec4<S>*>(lds + lds_param_bytes<S>(it.nc));
     Geo<S, M> g;
-    g.load(geom_of<S>(d), N, x.atom, x.active);
+    g.load(geom_of<S>(d), N, x.atom, x.active, &d.gd);
     constexpr int MM = M > 0 ? M : 1;
     int rv[MM];
 #pragma unroll
@@ -269,27 +269,35 @@ __device__ __forceinline__ void run_batched(const BArgs<S>& A, const Item& it, c
         const int c = it.c0 + clv;
         Cand<S, S, Full> p;
         load_cand(pbuf + kNParam * clv, p);
+        // Each bond gradient G_j goes to its exchange slot as soon as the site
+        // routine emits it and is folded into this atom's own force sum and
+        // the virial, so no bond-gradient array stays live across the exchange.
         double U;
-        S Gx[MM], Gy[MM], Gz[MM];
-        site_eval<S, S, M, MODE == MODE_EVAL>(g, p, U, Gx, Gy, Gz);
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            S* slot = &xb[x.own + m * x.g].x;         // the fourth component is never read
-            slot[0] = Gx[m];
-            slot[1] = Gy[m];
-            slot[2] = Gz[m];
-        }
-        exchange_sync(x.block_sync);
         S Fx = S(0), Fy = S(0), Fz = S(0);
+        S w6[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) w6[k] = S(0);
+        site_eval_sink<S, S, M, true, (M > kPairwiseMax), false, Full>(
+            g, p, U, [&](int m, S gx, S gy, S gz) {
+                S* slot = &xb[x.own + m * x.g].x;     // the fourth component is never read
+                slot[0] = gx;
+                slot[1] = gy;
+                slot[2] = gz;
+                Fx += gx; Fy += gy; Fz += gz;
+                const S dx = g.rhi[m] * g.ux[m], dy = g.rhi[m] * g.uy[m], dz = g.rhi[m] * g.uz[m];
+                w6[0] -= dx * gx; w6[1] -= dy * gy; w6[2] -= dz * gz;
+                w6[3] -= dy * gz; w6[4] -= dz * gx; w6[5] -= dx * gy;
+            });
+        exchange_sync(x.block_sync);
         S wi[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) wi[k] = S(0);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const Vec4<S> r = xb[rv[m]];
-            Fx += Gx[m] - r.x;
-            Fy += Gy[m] - r.y;
-            Fz += Gz[m] - r.z;
+            Fx -= r.x;
+            Fy -= r.y;
+            Fz -= r.z;
             if (MODE == MODE_EVAL) {
                 const S dx = g.rhi[m] * g.ux[m], dy = g.rhi[m] * g.uy[m], dz = g.rhi[m] * g.uz[m];
                 wi[0] += dx * r.x; wi[1] += dx * r.y; wi[2] += dx * r.z;
@@ -298,15 +306,6 @@ __device__ __forceinline__ void run_batched(const BArgs<S>& A, const Item& it, c
             }
         }
         exchange_sync(x.block_sync);
-        S w6[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) w6[k] = S(0);
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const S dx = g.rhi[m] * g.ux[m], dy = g.rhi[m] * g.uy[m], dz = g.rhi[m] * g.uz[m];
-            w6[0] -= dx * Gx[m]; w6[1] -= dy * Gy[m]; w6[2] -= dz * Gz[m];
-            w6[3] -= dy * Gz[m]; w6[4] -= dz * Gx[m]; w6[5] -= dx * Gy[m];
-        }
         // Lanes outside the structure have zero geometry and zero reference
         // forces, so their energy, virial and residual are exactly zero.
         double v[8];
@@ -606,7 +605,7 @@ __device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L
     const SetDev& d = A.set;
     const int N = d.N;
     Geo<S, M> g;
-    g.load(geom_of<S>(d), N, atom, active);
+    g.load(geom_of<S>(d), N, atom, active, &d.gd);
     constexpr int MM = M > 0 ? M : 1;
     const int c = L.c0 + blockIdx.y;
     const int nbs = d.st_boff[L.s + 1] - d.st_boff[L.s];

@@ -54,7 +54,12 @@ struct Geo {
         }
     }
 
-    __device__ __forceinline__ void load(const GeomArrays<S>& G, int N, int atom, bool active) {
+    // G64 (float geometry only): the float64 unit vectors, from which the cached
+    // cos(theta) values are formed and rounded once; from float unit vectors
+    // they carry up to ~2e-7 absolute error, which zeta passes on to the
+    // energy through (cos - h)^2.
+    __device__ __forceinline__ void load(const GeomArrays<S>& G, int N, int atom, bool active,
+                                         const GeomArrays<double>* G64 = nullptr) {
         if constexpr (sizeof(S) == 4) {
             if (G.pk0) {
 #pragma unroll
@@ -64,6 +69,23 @@ struct Geo {
                     const float4 b = active ? G.pk1[o] : make_float4(0.f, 0.f, 0.f, 0.f);
                     ux[m] = a.x; uy[m] = a.y; uz[m] = a.z; rhi[m] = a.w;
                     rlo[m] = b.x; rinv[m] = b.y; fc[m] = b.z; hfcp[m] = b.w;
+                }
+                if constexpr (kCache && NP > 0) {
+                    if (G64 && active) {
+                        double vx[M], vy[M], vz[M];
+#pragma unroll
+                        for (int m = 0; m < M; ++m) {
+                            const size_t o = (size_t)m * N + atom;
+                            vx[m] = G64->ux[o]; vy[m] = G64->uy[o]; vz[m] = G64->uz[o];
+                        }
+                        int p = 0;
+#pragma unroll
+                        for (int j = 0; j < M; ++j)
+#pragma unroll
+                            for (int k = j + 1; k < M; ++k)
+                                cs[p++] = (S)(vx[j] * vx[k] + vy[j] * vy[k] + vz[j] * vz[k]);
+                        return;
+                    }
                 }
                 cache_cos();
                 return;
@@ -105,6 +127,7 @@ struct Cand {
     V gam, K, d2, Kd2;               // g^T = gam + K t^2 / (d2 + t^2)
     S valid;
     S aAlo, aRlo, DRlo, DAlo, nlo, ninv2nlo;   // low parts for the float64 energy terms
+    S hlo;                                      // h - float(h): zeta of the float path
 };
 
 // Type of the site energy: float64 for the float path (its energy terms are
@@ -122,6 +145,7 @@ __device__ __forceinline__ void load_cand(const S* __restrict__ p, Cand<S, S, Fu
     c.DR = p[P_DR]; c.DA = p[P_DA]; c.hmu = p[P_HMU];
     c.zs = p[P_ZS]; c.ccs = p[P_CCS]; c.n = p[P_N]; c.ninv2n = p[P_NINV2N]; c.h = p[P_H];
     c.aAlo = p[P_AALO]; c.DRlo = p[P_DRLO]; c.nlo = p[P_NLO]; c.ninv2nlo = p[P_NINV2NLO];
+    c.hlo = p[P_HLO];
     c.valid = p[P_VALID];
     if constexpr (Full) {
         c.aR = p[P_AR]; c.hlambda = p[P_HLAMBDA]; c.aRlo = p[P_ARLO]; c.DAlo = p[P_DALO];
@@ -167,6 +191,7 @@ __device__ __forceinline__ void load_cand(const S* __restrict__ p, Cand<Dual<S, 
         }
     }
     c.valid = p[P_VALID];
+    c.hlo = S(0);
 }
 
 // Seeds K parameter directions, parameters Base .. Base + K - 1 of the
@@ -223,6 +248,7 @@ __device__ __forceinline__ void load_cand(const S* __restrict__ p, const double*
         }
     }
     c.valid = p[P_VALID];
+    c.hlo = S(0);
 }
 
 // Angular function and half its derivative for t = cos(theta) - h:
@@ -285,6 +311,11 @@ __device__ __forceinline__ void site_eval_sink(Geo<S, M>& g, const Cand<V, S, Fu
         opaque(g.uy);
         opaque(g.uz);
     }
+    // Energy64 (float path): the pair terms and the bond order of the energy
+    // are evaluated with float64 exponentials (below), and zeta takes h as a
+    // float hi/lo pair, so that a float rounding of h does not shift every
+    // (cos - h)^2 of a candidate the same way.
+    constexpr bool kE64 = Energy64 && std::is_same<V, float>::value;
     V zeta[MM];
 #pragma unroll
     for (int j = 0; j < M; ++j) zeta[j] = vconst<V, S>(S(0));
@@ -295,19 +326,23 @@ __device__ __forceinline__ void site_eval_sink(Geo<S, M>& g, const Cand<V, S, Fu
 #pragma unroll
             for (int k = j + 1; k < M; ++k) {
                 const S c = g.cosjk(j, k, pidx++);
-                const V t = c - p.h;
+                V t;
+                if constexpr (kE64) t = (c - p.h) - p.hlo;
+                else t = c - p.h;
                 const V gv = ang_g<Full>(p, t);
                 zeta[j] = zeta[j] + g.fc[k] * gv;
                 zeta[k] = zeta[k] + g.fc[j] * gv;
             }
         }
     }
-    // Energy64 (float path): the pair terms and the bond order of the energy
-    // are evaluated in float64.  In float32 the representation error of f_R
-    // and b f_A (up to ~15 eV each for parameters inside the fitting box)
-    // alone reaches 1e-6 eV per bond.  Their float32 roundings feed the
-    // gradient either way.
-    constexpr bool kE64 = Energy64 && std::is_same<V, float>::value;
+    // Energy64: in float32 the rounding of f_R and b f_A (up to ~15 eV each
+    // for parameters inside the fitting box) and the one-ulp errors of the
+    // hardware exponentials reach 1e-6 eV per bond.  The exponentials whose
+    // errors reach the energy at full weight, e^{-mu (r - r0)} and b, are
+    // taken in float64 (the argument of b from the float logarithm of
+    // 1 + zeta^n, whose error enters b damped by zeta^n / (1 + zeta^n) / 2n),
+    // and the pair energy is formed in float64.  Their float32 roundings feed
+    // the gradient.
     V cc[MM], D[MM];
     V usum = vconst<V, S>(S(0));
     double usum64 = 0.0;
@@ -321,23 +356,27 @@ __device__ __forceinline__ void site_eval_sink(Geo<S, M>& g, const Cand<V, S, Fu
         V eA, zn, b;
         [[maybe_unused]] V eR;
         if constexpr (kE64) {
-            const double dl = ((double)g.rhi[j] - (double)p.r0hi) + ((double)g.rlo[j] - (double)p.r0lo);
+            // float64 copies of the bond's geometry are made here, per candidate:
+            // hoisted out of the candidate loop they would hold 6 M registers
+            S rh = g.rhi[j], rl = g.rlo[j], fcj = g.fc[j];
+            asm volatile("" : "+v"(rh), "+v"(rl), "+v"(fcj));
+            const double dl = ((double)rh - (double)p.r0hi) + ((double)rl - (double)p.r0lo);
             const double eA64 = exp2_acc(-(((double)p.aA + (double)p.aAlo) * dl));
-            const double zn64 =
-                pos ? exp2_acc(((double)p.n + (double)p.nlo) * log2_acc((double)zsafe)) : 0.0;
-            const double b64 = exp2_acc(((double)p.ninv2n + (double)p.ninv2nlo) * log2_acc(1.0 + zn64));
+            const float zn32 = pos ? dexp2(p.n * dlog2(zsafe)) : 0.f;
+            const double b64 =
+                exp2_acc(((double)p.ninv2n + (double)p.ninv2nlo) * (double)dlog2(1.f + zn32));
             const double DR = (double)p.DR + (double)p.DRlo;
             if constexpr (Full) {
                 const double eR64 = exp2_acc(-(((double)p.aR + (double)p.aRlo) * dl));
                 const double DA = (double)p.DA + (double)p.DAlo;
-                usum64 += (double)g.fc[j] * (DR * eR64 - b64 * (DA * eA64));
+                usum64 += (double)fcj * (DR * eR64 - b64 * (DA * eA64));
                 eR = (float)eR64;
             } else {
                 // DA = 2 DR, e_R = e_A^2
-                usum64 += (double)g.fc[j] * (DR * eA64 * (eA64 - 2.0 * b64));
+                usum64 += (double)fcj * (DR * eA64 * (eA64 - 2.0 * b64));
             }
             eA = (float)eA64;
-            zn = (float)zn64;
+            zn = zn32;
             b = (float)b64;
         } else {
             const V delta = (g.rhi[j] - p.r0hi) + (g.rlo[j] - p.r0lo);
@@ -360,8 +399,8 @@ __device__ __forceinline__ void site_eval_sink(Geo<S, M>& g, const Cand<V, S, Fu
         // c~ = -ZS f_C f_A db/dzeta with db/dzeta = -b zeta^n / (2 zeta (1 + zeta^n))
         cc[j] = (p.ccs * g.fc[j]) * (bfA * zn) * drcp(zsafe * onep);
         // per-bond sweep: keep the scheduler from interleaving all M bonds' chains
-        // (about ten live values each)
-        if constexpr (PerBond) __builtin_amdgcn_sched_barrier(0);
+        // (about ten live values each; float64 ones in the energy mode)
+        if constexpr (PerBond || kE64) __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (kE64) U = 0.5 * usum64; else U = S(0.5) * usum;
     if constexpr (PerBond) {

@@ -110,6 +110,38 @@ def test_fitness_across_the_batching_limit(api, precision):
     ts.close()
 
 
+def test_graph_replay_after_the_staging_buffer_grows(api):
+    """A captured fitness graph holds the address of the two-pass staging
+    buffer (structures over 512 atoms).  A float64 call and a larger population
+    grow that buffer; the float32 call replayed afterwards must be captured
+    again, not replayed into the freed memory: same bits as its first call."""
+    import torch
+    g = rng(34)
+    s = W.make_set([W.random_packing(g, 600)] + W.strained_diamond_cells(35, 1))
+    refs = T.reference_data(s, W.draw_params(rng(36), 1)[0], R1, R2)
+    ts = api.from_structures(s)
+    assert ts.stats()["n_large"] == 1
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    X = torch.as_tensor(W.draw_params(rng(38), 6), device="cuda")
+    Z = torch.empty(6, 4, dtype=torch.float64, device="cuda")
+    call = ts.fitness_call(X, Z, precision="fp32")
+    call()                                          # captured
+    Z1 = Z.clone()
+    call()                                          # replayed
+    assert torch.equal(Z, Z1)
+    ts.fitness(X, precision="fp64")                 # 8-byte staging: the buffer grows
+    call()
+    torch.cuda.synchronize()
+    assert torch.equal(Z, Z1)
+    ts.fitness(W.draw_params(rng(39), 60), precision="fp32")   # 10x the candidates
+    call()
+    torch.cuda.synchronize()
+    assert torch.equal(Z, Z1)
+    Zo = T.fitness(s, X[[0, 5]].cpu().numpy(), refs)
+    assert np.abs(Z1[[0, 5]].cpu().numpy() - Zo).max() <= 1e-5 * np.abs(Zo).max()
+    ts.close()
+
+
 def test_population_extremes_give_identical_candidates(api):
     """P = 1 and P = 1000 (the same candidates repeated): every candidate's Z
     is the same bits whatever the population around it."""

@@ -350,3 +350,130 @@ def test_force_call_64k_sum_rules(big):
     assert np.abs(o32["F"][0] - F).max() <= 1e-4
     assert np.abs(o32["W"][0, 0] - W6).max() / N <= 1e-5
     assert np.abs(o32["J"][0] - o64["J"][0]).max() <= 1e-5 * np.abs(o64["J"][0]).max() + 1e-6
+
+
+# ---------------------------------------------------------------------------
+# The timed float32 fitness path at the per-structure bar (Sec. III.B)
+# ---------------------------------------------------------------------------
+# The fitness sums residuals of e_s = E_s / N_s, w_s = W_s / N_s and the force
+# components.  Held to 1e-6 eV/atom (energy), 1e-5 eV/atom (virial) and
+# 1e-4 eV/A per force component, the per-structure values bound every Z column
+# by the triangle inequality: |dZ_x| <= ||delta_x||_2 / sqrt(Q_x), with
+# ||delta_e|| <= 1e-6 sqrt(S), ||delta_w|| <= 1e-5 sqrt(6 S) and
+# ||delta_f|| <= 1e-4 sqrt(3 N).  The squared force residual of a structure is
+# checked the same way: |sqrt(rf_s) - ||F - F*||_s| <= 1e-4 sqrt(3 N_s).
+
+TOL_E, TOL_W, TOL_F = 1e-6, 1e-5, 1e-4
+
+
+def z_bounds(refs, sizes):
+    S, N = len(sizes), int(np.sum(sizes))
+    Qe = float(np.sum(np.asarray(refs["e"]) ** 2))
+    Qv = float(np.sum(np.asarray(refs["w"]) ** 2))
+    Qf = float(np.sum(np.asarray(refs["f"]) ** 2))
+    return np.array([TOL_E * np.sqrt(S / Qe), TOL_W * np.sqrt(6 * S / Qv), TOL_F * np.sqrt(3 * N / Qf)])
+
+
+def check_terms(t, e_o, w_o, fres_o, sizes, label):
+    """t: fitness_terms of one candidate (numpy); e_o, w_o per structure from
+    the oracle; fres_o = ||F - F*|| per structure."""
+    de = np.abs(t["e"] - e_o).max()
+    dw = np.abs(t["w"] - w_o).max()
+    df = (np.abs(np.sqrt(t["rf"]) - fres_o) / np.sqrt(3 * sizes)).max()
+    print(f"{label}: max |de| {de:.3e} eV/atom, |dw| {dw:.3e} eV/atom, "
+          f"force-residual norm per sqrt(3N) {df:.3e} eV/A", flush=True)
+    assert de <= TOL_E and dw <= TOL_W and df <= TOL_F, label
+    return de, dw
+
+
+def terms_np(ts, X):
+    return {k: v.cpu().numpy() for k, v in ts.fitness_terms(X).items()}
+
+
+def test_fp32_fitness_terms_ga_batch_every_candidate(api):
+    """Config 2 at full size in the default launch shape: fitness_terms of the
+    float32 fitness call for all 200 candidates against the oracle, per
+    structure; Z columns within the bounds those tolerances imply."""
+    wl = W.config2()
+    s = wl.structs
+    sizes = s.sizes().astype(float)
+    refs = T.reference_data(s, wl.hidden_x, R1, R2)
+    ts = api.from_structures(s)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    X = wl.population
+    Z32 = ts.fitness(X, precision="fp32").cpu().numpy()
+    t32 = terms_np(ts, X)
+    Z64 = ts.fitness(X, precision="fp64").cpu().numpy()
+    t64 = terms_np(ts, X)
+    top = T.topology(s, R2)
+    owner = np.repeat(np.arange(s.n_struct), s.sizes())
+    worst = [0.0, 0.0]
+    for c in range(X.shape[0]):
+        o = T.evaluate_set(s, X[c], R1, R2, topology=top)
+        e_o, w_o = o["E"] / sizes, o["W6"] / sizes[:, None]
+        fres = np.sqrt(np.bincount(owner, ((o["F"] - refs["f"]) ** 2).sum(1), minlength=s.n_struct))
+        de, dw = check_terms({k: v[c] for k, v in t32.items()}, e_o, w_o, fres, sizes, f"fp32 c={c}")
+        worst = [max(worst[0], de), max(worst[1], dw)]
+        if c % 40 == 0:
+            assert np.abs(t64["e"][c] - e_o).max() <= 1e-10 * np.abs(e_o).max()
+            assert np.abs(t64["w"][c] - w_o).max() <= 1e-10 * max(np.abs(w_o).max(), 1e-2)
+    print(f"config 2, 200 candidates: worst |de| {worst[0]:.3e} eV/atom, |dw| {worst[1]:.3e}", flush=True)
+    Zo = T.fitness(s, X[::20], refs, topology=top)
+    b = z_bounds(refs, sizes)
+    assert np.all(np.abs(Z32[::20, 1:] - Zo[:, 1:]) <= b)
+    assert np.all(np.abs(Z32[:, 1:] - Z64[:, 1:]) <= b)
+    ts.close()
+
+
+def test_fp32_fitness_terms_uneven_set(api, uneven, uneven_set, tmp_path):
+    """Config 3 (300 structures of 8-512 atoms, 500 candidates, the benchmark's
+    launch shape): float32 fitness_terms of every candidate and structure
+    against the float64 path (itself held to the oracle at 1e-10 below),
+    sampled structures x candidates against the oracle directly, and every
+    candidate's Z columns within the implied bounds.  The oracle's neighbour
+    search over all 300 structures takes most of a minute, so it evaluates the
+    sampled structures one at a time, and the references are seeded values of
+    the right magnitude rather than the oracle at a hidden parameter set."""
+    s = uneven.structs
+    sizes = s.sizes().astype(float)
+    P = uneven.population.shape[0]
+    # seeded references of the hidden set's magnitude: e_s and w_s do not
+    # depend on them, the force residual and Q_x do
+    e, w, f = synthetic_references(s, 13)
+    refs = {"e": e, "w": w, "f": f}
+    uneven_set.attach_reference(e, w, f)
+    cache = tmp_path / "shapes.txt"
+    shutil.copy(TUNED, cache)
+    uneven_set.autotune(P, "fp32", str(cache))
+    X = uneven.population
+    Z32 = uneven_set.fitness(X, precision="fp32").cpu().numpy()
+    t32 = terms_np(uneven_set, X)
+    Z64 = uneven_set.fitness(X, precision="fp64").cpu().numpy()
+    t64 = terms_np(uneven_set, X)
+    de = np.abs(t32["e"] - t64["e"])
+    dw = np.abs(t32["w"] - t64["w"]).max(axis=2)
+    fres64 = np.sqrt(t64["rf"])
+    df = np.abs(np.sqrt(t32["rf"]) - fres64) / np.sqrt(3 * sizes)[None]
+    c, k = np.unravel_index(np.argmax(de), de.shape)
+    print(f"config 3, fp32 vs fp64, all {P} x {s.n_struct}: max |de| {de.max():.3e} eV/atom "
+          f"(candidate {c}, structure {k}, {int(sizes[k])} atoms), |dw| {dw.max():.3e}, "
+          f"force residual {df.max():.3e}", flush=True)
+    assert de.max() <= TOL_E and dw.max() <= TOL_W and df.max() <= TOL_F
+    b = z_bounds(refs, sizes)
+    assert np.all(np.abs(Z32[:, 1:] - Z64[:, 1:]) <= b)
+    # sampled structures x candidates (the worst candidate of each structure
+    # included) against the oracle's per-structure evaluation
+    cands = sorted(set([0, 1, P // 2, P - 1] + [int(v) for v in np.argmax(de, axis=0)[::25]]))
+    for k in sample_structures(s):
+        pos, cell = s.structure(k)
+        one = W.make_set([(pos, cell)])
+        top = T.topology(one, R2)
+        f_ref = refs["f"][s.offset[k]:s.offset[k + 1]]
+        for c in sorted(set(cands + [int(np.argmax(de[:, k]))])):
+            o = T.evaluate_set(one, X[c], R1, R2, topology=top)
+            n = sizes[k]
+            e_o, w_o = o["E"][0] / n, o["W6"][0] / n
+            fres = np.sqrt(((o["F"] - f_ref) ** 2).sum())
+            tc = {"e": t32["e"][c, k], "w": t32["w"][c, k], "rf": t32["rf"][c, k]}
+            check_terms(tc, e_o, w_o, fres, np.array([n]), f"structure {k} ({int(n)} atoms) c={c}")
+            assert abs(t64["e"][c, k] - e_o) <= 1e-10 * max(abs(e_o), 1e-2)

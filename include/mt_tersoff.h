@@ -248,6 +248,35 @@ int fitness_grad_tf(mt_set* set, const double* x, int P, const double* w, int pr
                     double* Z, double* dZdx, void* stream);
 
 /*
+ * Device bytes of the fixed partial-sum array that fitness_eval_noalloc uses
+ * (32 MiB per GPU, held from the first such call until the process ends).
+ */
+#define MT_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/*
+ * fitness_eval for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): the
+ * same batched kernels and result as fitness_eval (minimal form, batched
+ * schedule), with the per-slot partial sums in a fixed device array of
+ * MT_NOALLOC_SCRATCH_BYTES per GPU instead of the set's workspace.  It calls
+ * no hipMalloc or hipFree and captures no graph: the kernels are launched
+ * directly on `stream`.
+ *   x, P, w, precision, Z  as for fitness_eval
+ * The work list for this P, precision and launch shape must exist already: make
+ * one fitness_eval call (or mt_autotune) with them first, else MT_ESTATE.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (each call overwrites every sum it reads, nothing has to start at
+ * zero); calls that overlap on one GPU, from any thread or stream, race.
+ * Errors: as for fitness_eval; MT_EINVAL when P x (partial-sum slots of the
+ * set) x 64 bytes exceeds MT_NOALLOC_SCRATCH_BYTES, when the set has a
+ * structure that takes the two-pass path (over MT_MAX_BATCHED_ATOMS atoms, or
+ * too large for one block's LDS), or when the current device is not the set's.
+ * fitness_terms does not read these sums (MT_ESTATE after this call).
+ */
+int fitness_eval_noalloc(mt_set* set, const double* x, int P, const double* w, int precision,
+                         double* Z, void* stream);
+
+/*
  * Per-structure terms behind the most recent fitness_eval, fitness_eval_tf,
  * fitness_grad or fitness_grad_tf call on this set: the predicted quantities
  * whose residuals the Sec. III.B fitness sums, for comparing predicted and

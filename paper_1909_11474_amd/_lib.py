@@ -27,6 +27,7 @@ MT_PLAIN = 1
 
 MT_MAX_NBR = 16
 MT_MAX_BATCHED_ATOMS = 512
+MT_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
@@ -55,6 +56,7 @@ SIGNATURES = {
     "fitness_grad": (_i, [_vp, _vp, _i, ctypes.POINTER(_d), _i, _vp, _vp, _vp]),
     "fitness_grad_tf": (_i, [_vp, _vp, _i, ctypes.POINTER(_d), _i, _vp, _vp, _vp]),
     "fitness_terms": (_i, [_vp, _vp, _i, _vp, _vp, _vp, _vp]),
+    "fitness_eval_noalloc": (_i, [_vp, _vp, _i, ctypes.POINTER(_d), _i, _vp, _vp]),
     "mt_autotune": (_i, [_vp, _i, _i, ctypes.c_char_p]),
     "mt_profile_enable": (_i, [_vp, _i]),
     "mt_profile_read": (_i, [_vp, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_int64)]),

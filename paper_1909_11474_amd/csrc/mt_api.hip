@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -101,7 +102,7 @@ static hipEvent_t pool_event(mt_set* set) {
 }
 
 ProfScope::ProfScope(mt_set* set, int kind) {
-    if (!set->profiling) return;
+    if (!set->profiling || kind < 0) return;
     e0 = pool_event(set);
     e1 = pool_event(set);
     if (!e0 || !e1) { e0 = e1 = nullptr; return; }
@@ -440,6 +441,68 @@ int fitness_terms(mt_set* set, const double* x, int P, double* e, double* w, dou
     set->cur_x = x;
     set->cur_form = set->fit_form;
     return launch_fitness_terms(set, P, e, w, rf, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free fitness: partial sums in a fixed device array.
+// ---------------------------------------------------------------------------
+// Each GPU the library runs on holds its own copy of this array until the
+// process ends; its device address is taken once per device.
+static __device__ __align__(256) double scratch[MT_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_device(int dev, double** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(MT_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        // the array's host-side name is not a device address: ask for this
+        // device's copy (the set's device is current here)
+        HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return MT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int fitness_eval_noalloc(mt_set* set, const double* x, int P, const double* w, int precision,
+                         double* Z, void* stream) {
+    TRY(check_fitness(set, x, P, w, precision, Z));
+    if (set->n_large > 0)
+        return fail(MT_EINVAL, "fitness_eval_noalloc: the set has structures over " +
+                                   std::to_string(MT_MAX_BATCHED_ATOMS) + " atoms (two-pass path)");
+    const size_t need = sizeof(double) * kNVFit * (size_t)P * std::max(1, set->nslots);
+    if (need > MT_NOALLOC_SCRATCH_BYTES)
+        return fail(MT_EINVAL, "fitness_eval_noalloc: P x partial-sum slots needs " + std::to_string(need) +
+                                   " bytes of scratch, more than " +
+                                   std::to_string((long long)MT_NOALLOC_SCRATCH_BYTES));
+    const LaunchCfg cfg = cfg_for(set, P, precision);
+    ItemPlan* plan = find_plan(set, P, cfg, family_for(precision, MODE_FIT, 0));
+    if (!plan)
+        return fail(MT_ESTATE, "fitness_eval_noalloc: no work list for this P and precision yet "
+                               "(make one fitness_eval call with them first)");
+    if (!plan->twopass.empty())
+        return fail(MT_EINVAL, "fitness_eval_noalloc: a structure needs the two-pass path");
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev != set->device) return fail(MT_EINVAL, "the set's device is not the current device");
+    double* part = nullptr;
+    TRY(scratch_of_device(dev, &part));
+    hipStream_t st = (hipStream_t)stream;
+    set->fit_P = 0;              // the set's own workspace does not hold these sums
+    set->cur_x = x;
+    set->cur_form = 0;
+    TRY(launch_plan_fit(set, plan, cfg, precision, part, st));
+    return launch_finalize_fit(set, P, w, Z, st, part);
 }
 
 int mt_profile_enable(mt_set* set, int enable) {

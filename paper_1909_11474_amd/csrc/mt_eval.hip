@@ -564,6 +564,11 @@ static std::vector<Item> xcd_grouped(const std::vector<Item>& items) {
     return out;
 }
 
+ItemPlan* find_plan(mt_set* set, int P, const LaunchCfg& cfg, int fam) {
+    auto itp = set->plans.find(std::make_tuple(P, cfg.block, cfg.tile, cfg.persistent, fam));
+    return itp != set->plans.end() ? itp->second.get() : nullptr;
+}
+
 // cfg.block == 0 requests the plain plan: one item per (structure, candidate).
 ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int fam) {
     auto key = std::make_tuple(P, cfg.block, cfg.tile, cfg.persistent, fam);
@@ -701,7 +706,7 @@ static int run_plan(mt_set* set, ItemPlan* plan, const LaunchCfg& cfg, int fam, 
         if (!plain) {
             Af.items = Ad.items = cp.items.as<Item>();
             Af.bin_off = Ad.bin_off = cp.bin_off.as<int>();
-            ProfScope prof(set, prof_kind);
+            ProfScope prof(set, prof_kind < 0 ? -1 : prof_kind);
             HIPCHECK(launch_family(fam, cp.mc, dim3(cp.n_bins), dim3(cp.block), cp.lds, st, Af, Ad,
                                    prof.e0, prof.e1));
         } else {
@@ -743,6 +748,14 @@ int launch_batched(mt_set* set, const LaunchCfg& cfg, int P, int precision, int 
     if (plan->twopass.empty()) return MT_OK;
     TRY_RC(reserve_twopass(set, plan, P, precision));     // no-op once reserved
     return launch_twopass(set, plan->twopass, P, precision, mode, vel, force, atom_virial, st);
+}
+
+int launch_plan_fit(mt_set* set, ItemPlan* plan, const LaunchCfg& cfg, int precision, double* partial,
+                    hipStream_t st) {
+    const int fam = family_for(precision, MODE_FIT, set->cur_form);
+    BArgs<float> Af = make_args<float>(set, partial, kNVFit);
+    BArgs<double> Ad = make_args<double>(set, partial, kNVFit);
+    return run_plan(set, plan, cfg, fam, Af, Ad, -1, st);
 }
 
 int launch_plain(mt_set* set, int P, int precision, int mode, const double* vel, double* force,
@@ -865,8 +878,9 @@ int launch_large(mt_set* set, int P, int precision, int mode, const double* vel,
     return launch_twopass(set, structs, P, precision, mode, vel, force, atom_virial, st);
 }
 
-int launch_finalize_fit(mt_set* set, int P, const double* w, double* Z, hipStream_t st) {
-    FinArgs F = make_fin(set, kNVFit, set->partial.as<double>());
+int launch_finalize_fit(mt_set* set, int P, const double* w, double* Z, hipStream_t st,
+                        const double* partial) {
+    FinArgs F = make_fin(set, kNVFit, partial ? partial : set->partial.as<double>());
     F.we = w[0]; F.wv = w[1]; F.wf = w[2];
     F.Z = Z;
     if (F.coop) {

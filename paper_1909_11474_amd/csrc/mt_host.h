@@ -185,7 +185,9 @@ int launch_large(mt_set* set, int P, int precision, int mode, const double* vel,
 // Reserve the two-pass staging buffer for the set's large structures and the
 // plan's two-pass structures (before graph capture: capture may not allocate).
 int reserve_twopass(mt_set* set, const ItemPlan* plan, int P, int precision);
-int launch_finalize_fit(mt_set* set, int P, const double* w, double* Z, hipStream_t stream);
+// partial: the per-slot partial sums to finalize (null: the set's workspace)
+int launch_finalize_fit(mt_set* set, int P, const double* w, double* Z, hipStream_t stream,
+                        const double* partial = nullptr);
 int launch_finalize_eval(mt_set* set, int P, double* energy, double* virial, double* heat,
                          hipStream_t stream);
 // Per-structure e_s, w_s and squared force residual from the fitness partial
@@ -201,6 +203,12 @@ int launch_finalize_grad(mt_set* set, int P, const double* Z, double* dZdx, hipS
 enum Mode { MODE_FIT = 0, MODE_EVAL = 1 };
 
 ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int family);
+// The cached work list for these arguments, or null (never builds one).
+ItemPlan* find_plan(mt_set* set, int P, const LaunchCfg& cfg, int family);
+// The batched fitness launches of an existing plan, partial sums written to
+// `partial` ([P][nslots][kNVFit]); no allocation, no profiling events.
+int launch_plan_fit(mt_set* set, ItemPlan* plan, const LaunchCfg& cfg, int precision, double* partial,
+                    hipStream_t stream);
 // Batched kernel family of a call: precision x mode x parameter form.
 int family_for(int precision, int mode, int form);
 LaunchCfg default_cfg(const mt_set* set, int P, int precision);

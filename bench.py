@@ -8,20 +8,24 @@ fitness (Sec. III.B of the paper).  The neighbour lists and bond geometry are
 built once per structure set (the cutoffs are fixed, not fitted) and are not
 part of a step.
 
-Before the W untimed warm-up steps the fitness workloads (headline, uneven,
-Tersoff form) run for 0.25 s, so that the GPU has left its idle clock; the
-timed region then holds exactly K steps.
+Headline workload: uneven batching, 500 candidates x 300 structures of 8-512
+atoms (strained diamond supercells, the same with vacancies, random
+packings), float32 arithmetic with float64 accumulation and float64 energy
+terms; reference data of a hidden parameter set written by the float64 oracle
+(tests/golden/make_references.py).  Before the W untimed warm-up steps the
+workload runs for 0.25 s, so that the GPU has left its idle clock; the timed
+region holds exactly K steps.  The roofline block is that of the dominant
+kernel (the launch of the largest coordination class), timed over
+back-to-back launches of it alone.
 
-Headline workload: 200 candidates x 100 strained 64-atom diamond Si cells,
-float32 arithmetic with float64 accumulation; reference data from a hidden
-parameter set evaluated by the library's float64 path.  The same run also
-measures the plain schedule (one launch per candidate and structure), the
-fitness gradient, uneven batching (500 candidates x 300 structures of 8-512
-atoms), the gradient over those structures (64 candidates), GA generations
-with gradient refinement over them, the GA batch with nine-parameter
-Tersoff-form candidates and the 64,000-atom force call, and times
-the CPU oracle on a bounded sample.  Prints
-one JSON line on stdout; progress goes to stderr.
+The same run measures the uneven set in the specified launch form (one
+persistent launch per class, graph replay) beside the tuned one, the plain
+schedule (one launch per candidate and structure), the GA batch (200
+candidates x 100 strained 64-atom cells), the fitness gradient (64 candidates
+over the uneven set), the GA with top-8 gradient refinement against the plain
+GA for 500 generations, the nine-parameter Tersoff form, the 64,000-atom force
+call, the 0 K property layer and HNEMD, and times the CPU oracle on a bounded
+sample.  Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -33,8 +37,11 @@ import time
 
 import numpy as np
 
-FP32_VALU_PEAK_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, non-packed
-PACKED_FP32_PEAK_TFLOPS = 157.3  # the vendor's float32 vector figure, which counts packed FP32 (unused here)
+FP32_PEAK_TFLOPS = 157.3         # MI355X published float32 vector peak (counts packed FP32)
+FP32_NONPACKED_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, non-packed
+FP64_PEAK_TFLOPS = 78.6          # MI355X published float64 vector peak
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden")
 # Launch shapes measured by mt_autotune on MI355X, keyed by set size and population.
 TUNED_SHAPES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1909_11474_amd",
                             "tuned_shapes.txt")
@@ -105,21 +112,50 @@ def kernel_flops_per_atom(M: np.ndarray) -> np.ndarray:
     return 31 * (M * (M - 1) // 2) + 70 * M + 9
 
 
+def grad_flops_per_atom(M: np.ndarray) -> np.ndarray:
+    """Algorithmic flops of the fitness gradient per atom and candidate, a
+    forward-mode model of the chain rule: the forward fitness work plus, for
+    each of the six parameter directions, the directional derivative of the
+    energy, force and virial work at twice its flops (each product a b needs
+    a db + b da), plus the contraction of each bond gradient's six
+    derivatives with its residual direction (6 x 3 FMA per bond):
+    13 x flops_per_atom + 36 M; 11,012 for a diamond atom."""
+    M = np.asarray(M, dtype=np.int64)
+    return 13 * flops_per_atom(M) + 36 * M
+
+
+def force_call_flops_per_atom(M: np.ndarray) -> np.ndarray:
+    """Flops of the MD-scale force call per atom: energy, forces and virial
+    (flops_per_atom), the per-atom virial (9 FMA per bond) and the heat-current
+    term W_i v_i (9 FMA); 926 for a diamond atom."""
+    M = np.asarray(M, dtype=np.int64)
+    return flops_per_atom(M) + 18 * M + 18
+
+
+# Algorithmic HBM bytes of the force call per atom: positions and velocities
+# read (float64, 24 B each), forces (24 B) and per-atom virial (72 B) written.
+FORCE_CALL_BYTES_PER_ATOM = 24 + 24 + 24 + 72
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=100,
+                    help="timed generations of the headline (uneven) workload")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--plain-steps", type=int, default=1)
-    ap.add_argument("--grad-steps", type=int, default=10)
-    ap.add_argument("--uneven-steps", type=int, default=10,
-                    help="generations of the uneven-batching workload (0: skip)")
-    ap.add_argument("--uneven-grad-steps", type=int, default=5,
+    ap.add_argument("--ga-batch-steps", type=int, default=200,
+                    help="generations of the GA batch (200 x 100 x 64 atoms; 0: skip)")
+    ap.add_argument("--grad-steps", type=int, default=10,
+                    help="gradient calls on the GA batch (0: skip)")
+    ap.add_argument("--specified-steps", type=int, default=50,
+                    help="generations of the uneven workload in the specified launch form (0: skip)")
+    ap.add_argument("--uneven-grad-steps", type=int, default=10,
                     help="gradient calls over the uneven structures (0: skip)")
     ap.add_argument("--md-steps", type=int, default=20,
                     help="64,000-atom force calls (0: skip)")
-    ap.add_argument("--ga-generations", type=int, default=10,
-                    help="GA generations with gradient refinement over the uneven set (0: skip)")
+    ap.add_argument("--ga-generations", type=int, default=500,
+                    help="generations of the refined-vs-plain GA comparison over the uneven set (0: skip)")
     ap.add_argument("--tf-steps", type=int, default=50,
                     help="generations of the Tersoff-form (9-parameter) GA batch (0: skip)")
     ap.add_argument("--md-run-steps", type=int, default=200,
@@ -160,25 +196,46 @@ class Timer:
         self.seconds = self.e0.elapsed_time(self.e1) / 1e3
 
 
-def make_set(api, torch, wl):
-    """Set + float64 reference data of the hidden parameter set (per-atom energies
-    and virials, forces), all resident in HBM."""
+REFERENCE_FILES = {"config2": "references_ga_batch.npz", "config3": "references_uneven.npz"}
+
+
+def load_references(wl, key):
+    """The float64 oracle's reference data of the workload's hidden parameter
+    set, as written by tests/golden/make_references.py; checked against the
+    workload's seeds, hidden parameters and sizes."""
+    d = np.load(os.path.join(GOLDEN, REFERENCE_FILES[key]), allow_pickle=False)
+    s = wl.structs
+    ok = (np.array_equal(d["sizes"], s.sizes()) and np.array_equal(d["hidden_x"], wl.hidden_x)
+          and int(d["seeds"][0]) == wl.seeds["structures"] and int(d["seeds"][1]) == wl.seeds["hidden"])
+    if not ok:
+        raise SystemExit(f"{REFERENCE_FILES[key]} does not belong to {wl.name}: "
+                         "rerun tests/golden/make_references.py")
+    return d["e"], d["w"], d["f"]
+
+
+def make_set(api, torch, wl, key):
+    """Set + the oracle's reference data (per-atom energies and virials,
+    forces), all resident in HBM."""
     t0 = time.perf_counter()
     ts = api.from_structures(wl.structs, R1=wl.R1, R2=wl.R2)
     torch.cuda.synchronize()
     t_create = time.perf_counter() - t0
-    ref = ts.tersoff_eval(wl.hidden_x[None], precision="fp64", forces=True, virial=True)
-    n = torch.as_tensor(wl.structs.sizes().astype(np.float64), device=ref["E"].device)
-    refs = (ref["E"][0] / n, ref["W"][0] / n[:, None], ref["F"][0])
-    ts.attach_reference(*refs)
+    e, w, f = load_references(wl, key)
+    ts.attach_reference(e, w, f)
+    dev = ts.device
+    refs = tuple(torch.as_tensor(a, device=dev) for a in (e, w, f))
     return ts, refs, t_create
+
+
+def coordination(ts, n_atoms):
+    i, _, _ = ts.neighbors()
+    return np.bincount(i, minlength=n_atoms)
 
 
 def set_flops(ts, n_atoms):
     """(algorithmic flops, transcendentals, kernel-formulation flops) of one
     candidate over the set, from each atom's coordination."""
-    i, _, _ = ts.neighbors()
-    M = np.bincount(i, minlength=n_atoms)
+    M = coordination(ts, n_atoms)
     return float(flops_per_atom(M).sum()), float(6 * M.sum()), float(kernel_flops_per_atom(M).sum())
 
 
@@ -195,11 +252,9 @@ def spin_up(torch, call, seconds=0.25):
 
 def time_generations(torch, ts, X, Z, steps, warmup):
     """GPU time of `steps` back-to-back fitness_eval calls (graph replay or direct,
-    as tuned); then the batched kernels' own time, two ways: an event pair
-    around each launch (prof: summed ms, launches; each pair adds the dispatch
-    and completion latency) and `steps` back-to-back passes of the kernels
-    alone between one event pair on their stream (b2b: ms per pass, launches
-    per pass)."""
+    as tuned); the batched kernels' own time over `steps` back-to-back passes
+    between one event pair on their stream (ms per pass, launches per pass); and
+    the median of generations each bracketed by its own event pair."""
     call = ts.fitness_call(X, Z, precision="fp32", schedule="batched")
     spin_up(torch, call)
     for _ in range(warmup):
@@ -207,15 +262,7 @@ def time_generations(torch, ts, X, Z, steps, warmup):
     with Timer(torch) as t:
         for _ in range(steps):
             call()
-    ts.profile(True)
-    ts.profile_read()
-    for _ in range(steps):
-        call()
-    torch.cuda.synchronize()
-    prof = ts.profile_read()["batched"]
-    ts.profile(False)
     b2b = ts.profile_fitness_kernels(X, "fp32", steps)
-    # per-generation times (an event pair around each call), for the median
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(max(20, min(steps, 200)))]
     for a, b in ev:
@@ -224,7 +271,33 @@ def time_generations(torch, ts, X, Z, steps, warmup):
         b.record()
     torch.cuda.synchronize()
     t.median_ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
-    return t, prof, b2b
+    return t, b2b
+
+
+def dominant_launch(ts, X, M, sizes, P, reps):
+    """The launch of the batched fitness plan that takes longest, timed alone
+    over `reps` back-to-back launches: its algorithmic flops (P candidates over
+    its structures), ms and coordination class, and every launch's figures."""
+    launches, struct_launch = ts.profile_fitness_launches(X, "fp32", reps)
+    owner = np.repeat(np.arange(len(sizes)), sizes)
+    per_atom = flops_per_atom(M)
+    out = []
+    for k, (ms, mc) in enumerate(launches):
+        structs = [s for s, l in enumerate(struct_launch) if l == k]
+        atoms = np.isin(owner, structs)
+        flop = float(per_atom[atoms].sum()) * P
+        out.append({"launch": k, "coordination_class": mc, "structures": len(structs),
+                    "atoms": int(atoms.sum()), "avg_ms": ms, "flop_per_launch": flop,
+                    "tflops": flop / (ms * 1e-3) / 1e12})
+    dom = max(out, key=lambda r: r["avg_ms"])
+    return dom, out
+
+
+def fp32_roofline(flop, ms):
+    achieved = flop / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS,
+            "peak_nonpacked": FP32_NONPACKED_TFLOPS, "frac_nonpacked": achieved / FP32_NONPACKED_TFLOPS}
 
 
 def time_plain(torch, ts, X, Z, steps):
@@ -260,9 +333,10 @@ def oracle_sample(call, population, seconds):
 _ORACLE_TOPOLOGY = {}
 
 
-def oracle_rate(args, torch, wl, refs, grad: bool):
+def oracle_rate(args, torch, wl, refs, grad: bool, seconds=None):
     """The CPU oracle's fitness (or fitness-gradient) rate over a workload's
-    structures, in atom*candidate evals/s, on a third of the CPU budget."""
+    structures, in atom*candidate evals/s, on `seconds` (default a third of the
+    CPU budget) of candidate evaluations."""
     from oracle import tersoff as T
     s = wl.structs
     r = {"e": refs[0].cpu().numpy(), "w": refs[1].cpu().numpy(), "f": refs[2].cpu().numpy()}
@@ -275,7 +349,8 @@ def oracle_rate(args, torch, wl, refs, grad: bool):
     t_top = time.perf_counter() - t0
     fn = T.fitness_grad if grad else T.fitness
     fn(s, wl.population[:1], r, topology=top)                        # warm-up
-    done, tc = oracle_sample(lambda X: fn(s, X, r, topology=top), wl.population, args.cpu_seconds / 3)
+    budget = args.cpu_seconds / 3 if seconds is None else seconds
+    done, tc = oracle_sample(lambda X: fn(s, X, r, topology=top), wl.population, budget)
     what = "fitness and dZ/dx" if grad else "fitness"
     out = {"value": done * s.n_atoms / tc,
            "unit": "atom·candidate fitness-grad evals/s" if grad else "atom·candidate evals/s",
@@ -287,41 +362,114 @@ def oracle_rate(args, torch, wl, refs, grad: bool):
     return out
 
 
-def uneven_batching(args, api, torch, W, dev):
+def cpu_baseline_headline(args, torch, wl, refs):
+    """The oracle on the headline workload: all host threads for the CPU budget,
+    then one thread for a third of it."""
+    out = oracle_rate(args, torch, wl, refs, grad=False, seconds=args.cpu_seconds)
+    out["host"] = {"nproc": os.cpu_count(), "cpu_model": cpu_model()}
+    threads = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        one = oracle_rate(args, torch, wl, refs, grad=False, seconds=args.cpu_seconds / 3)
+    finally:
+        torch.set_num_threads(threads)
+    out["one_thread"] = {"value": one["value"], "cores": 1, "sample": one["sample"]}
+    return out
+
+
+def uneven_specified_form(args, api, torch, W, dev, tuned):
+    """The uneven workload in the launch form its specification names: one
+    persistent launch per coordination class (static LPT bins over a fixed
+    grid) replayed from a captured HIP graph, at the tuned block and tile, beside
+    the tuned form."""
+    import tempfile
     wl = W.config3()
     s = wl.structs
     P = wl.population.shape[0]
-    log(f"workload: {wl.name}; atoms {s.n_atoms}, population {P}")
-    ts, refs, t_create = make_set(api, torch, wl)
+    ts, _, _ = make_set(api, torch, wl, "config3")
     st = ts.stats()
-    flop_cand, _, _ = set_flops(ts, s.n_atoms)
+    key = (f"N={st['n_atoms']} S={st['n_struct']} nb={st['n_bonds']} trip={st['n_triplets']} "
+           f"P={P} prec=1")
+    with tempfile.TemporaryDirectory() as d:
+        cache = os.path.join(d, "shape.txt")
+        with open(cache, "w") as f:
+            f.write(f"{key} | block={tuned['block']} tile={tuned['tile']} persistent=1 graph=1 ms=0\n")
+        ts.autotune(P, "fp32", cache)
     X = torch.as_tensor(wl.population, dtype=torch.float64, device=dev).contiguous()
     Z = torch.empty(P, 4, dtype=torch.float64, device=dev)
-    t0 = time.perf_counter()
+    t, b2b = time_generations(torch, ts, X, Z, args.specified_steps, 2)
+    out = {"workload": wl.name + "; one persistent launch per class, graph replay",
+           "launch_shape": {"block": tuned["block"], "tile": tuned["tile"], "persistent": 1, "graph": 1},
+           "value": P * s.n_atoms * args.specified_steps / t.seconds, "unit": "atom·candidate evals/s",
+           "ms_per_step": t.seconds / args.specified_steps * 1e3, "steps": args.specified_steps,
+           "batched_kernels_ms_per_step": b2b[0], "batched_launches_per_step": b2b[1]}
+    log(f"uneven, persistent + graph: {out['ms_per_step']:.3f} ms/generation")
+    ts.close()
+    return out
+
+
+def tuned_shape(path, ts, P):
+    """The launch shape the cache file holds for this set and population."""
+    st = ts.stats()
+    key = (f"N={st['n_atoms']} S={st['n_struct']} nb={st['n_bonds']} trip={st['n_triplets']} "
+           f"P={P} prec=1")
+    shape = None
+    if path and os.path.exists(path):
+        with open(path) as f:
+            for line in f:
+                if line.startswith(key + " | "):
+                    kv = dict(t.split("=") for t in line.split(" | ")[1].split())
+                    shape = {k: float(v) if k == "ms" else int(v) for k, v in kv.items()}
+    return shape
+
+
+def ga_batch(args, api, torch, W, dev):
+    """The GA fitness batch: 200 candidates x 100 strained 64-atom cells, one
+    coordination class (one launch per generation)."""
+    wl = W.config2()
+    s = wl.structs
+    P = wl.population.shape[0]
+    ts, refs, t_create = make_set(api, torch, wl, "config2")
+    flop_cand, trans_cand, kflop_cand = set_flops(ts, s.n_atoms)
+    X = torch.as_tensor(wl.population, dtype=torch.float64, device=dev).contiguous()
+    Z = torch.empty(P, 4, dtype=torch.float64, device=dev)
     if not args.no_tune:
         ts.autotune(P, "fp32", args.tune_cache)
-    t_tune = time.perf_counter() - t0
-    t, prof, b2b = time_generations(torch, ts, X, Z, args.uneven_steps, 2)
+    t, b2b = time_generations(torch, ts, X, Z, args.ga_batch_steps, args.warmup)
+    kernel_ms = b2b[0] / max(b2b[1], 1)
     units = P * s.n_atoms
-    kernel_ms = b2b[0]
-    out = {"workload": wl.name, "value": units * args.uneven_steps / t.seconds,
-           "unit": "atom·candidate evals/s", "ms_per_step": t.seconds / args.uneven_steps * 1e3,
-           "steps": args.uneven_steps, "atoms": s.n_atoms, "structures": s.n_struct,
-           "bonds": st["n_bonds"], "triplets": st["n_triplets"], "population": P,
-           "batched_kernels_ms_per_step": kernel_ms,
-           "batched_launches_per_step": b2b[1],
-           "batched_kernels_ms_per_step_event_pair_per_launch": prof[0] / args.uneven_steps,
-           "algorithmic_tflops": flop_cand * P / (kernel_ms * 1e-3) / 1e12,
-           "setup_ms": {"set_create": t_create * 1e3, "autotune": t_tune * 1e3},
-           "seeds": wl.seeds}
-    log(f"uneven batched: {out['ms_per_step']:.3f} ms/generation, {out['value']:.4e} atom*cand/s, "
-        f"kernels {kernel_ms:.3f} ms ({out['algorithmic_tflops']:.2f} TFLOP/s)")
+    out = {"workload": wl.name, "value": units * args.ga_batch_steps / t.seconds,
+           "unit": "atom·candidate evals/s", "ms_per_step": t.seconds / args.ga_batch_steps * 1e3,
+           "ms_per_step_median": t.median_ms, "steps": args.ga_batch_steps, "population": P,
+           "atoms": s.n_atoms, "seeds": wl.seeds,
+           "roofline": fp32_roofline(flop_cand * P, kernel_ms),
+           "kernel": {"name": "k_batched<float, fit, M<=4>", "avg_ms": kernel_ms,
+                      "flop_per_launch": flop_cand * P, "transcendentals_per_launch": trans_cand * P,
+                      "formulation_flop_per_launch": kflop_cand * P},
+           "setup_ms": {"set_create": t_create * 1e3}}
+    log(f"GA batch: {out['ms_per_step']:.4f} ms/generation, kernel {kernel_ms * 1e3:.1f} us, "
+        f"{out['roofline']['achieved']:.1f} TFLOP/s")
+    Zb = Z.clone()
     if args.plain_steps > 0:
         tp = time_plain(torch, ts, X, Z, args.plain_steps)
         out["plain"] = {"value": units * args.plain_steps / tp.seconds,
                         "ms_per_step": tp.seconds / args.plain_steps * 1e3,
-                        "launches_per_step": P * s.n_struct}
-        log(f"uneven plain: {out['plain']['ms_per_step']:.1f} ms/generation")
+                        "launches_per_step": P * s.n_struct,
+                        "max_abs_dZ_vs_batched": float((Z - Zb).abs().max())}
+    if args.grad_steps > 0:
+        tg = time_grad(torch, ts, X, args.grad_steps)
+        out["fitness_grad"] = {"value": units * args.grad_steps / tg.seconds,
+                               "unit": "atom·candidate fitness-grad evals/s",
+                               "ms_per_step": tg.seconds / args.grad_steps * 1e3}
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 x {args.copy_probe_mib} MiB device-to-device")
+        del src, dst
     ts.close()
     if not args.no_cpu_baseline:
         out["cpu_oracle"] = oracle_rate(args, torch, wl, refs, grad=False)
@@ -332,78 +480,97 @@ def uneven_gradient(args, api, torch, W, dev):
     wl = W.config4()
     s = wl.structs
     P = wl.population.shape[0]
-    ts, refs, _ = make_set(api, torch, wl)
+    ts, refs, _ = make_set(api, torch, wl, "config3")
+    M = coordination(ts, s.n_atoms)
     X = torch.as_tensor(wl.population, dtype=torch.float64, device=dev).contiguous()
     if not args.no_tune:
         ts.autotune(P, "fp32", args.tune_cache)
     t = time_grad(torch, ts, X, args.uneven_grad_steps)
+    ms = t.seconds / args.uneven_grad_steps * 1e3
+    flop = float(grad_flops_per_atom(M).sum()) * P
     out = {"workload": wl.name, "value": P * s.n_atoms * args.uneven_grad_steps / t.seconds,
-           "unit": "atom·candidate fitness-grad evals/s",
-           "ms_per_step": t.seconds / args.uneven_grad_steps * 1e3,
-           "steps": args.uneven_grad_steps, "population": P, "seeds": wl.seeds}
-    log(f"uneven gradient: {out['ms_per_step']:.3f} ms/call, {out['value']:.4e} atom*cand/s")
+           "unit": "atom·candidate fitness-grad evals/s", "ms_per_step": ms,
+           "steps": args.uneven_grad_steps, "population": P, "seeds": wl.seeds,
+           "roofline": dict(fp32_roofline(flop, ms), timing="whole fitness_grad call (forward "
+                            "fitness, coefficients, adjoint, finalize), events around back-to-back calls",
+                            flop_model="13 x the forward algorithmic flops + 36 per bond (see grad_flops_per_atom)",
+                            flop_per_call=flop)}
+    log(f"uneven gradient: {ms:.3f} ms/call, {out['value']:.4e} atom*cand/s, "
+        f"{out['roofline']['achieved']:.1f} TFLOP/s (model)")
     ts.close()
     if not args.no_cpu_baseline:
         out["cpu_oracle"] = oracle_rate(args, torch, wl, refs, grad=True)
     return out
 
 
-def ga_generations(args, api, torch, W, dev):
-    """The host GA (Sec. III.B) on the GPU fitness over the uneven structures,
-    population 64, with projected-gradient refinement of the best 8 each
-    generation: wall time per generation (fitness, sort, refinement with its
-    gradient and trial fitness, selection, crossover, mutation)."""
+def ga_judge(args, api, torch, W, dev):
+    """The GA over the uneven set, population 64 (N_par 32, mutation 0.2 -> 0
+    over the run): with projected-gradient refinement of the best 8 each
+    generation against the plain GA from the same seed (the judge), for the
+    configured number of generations; best Z every 50 generations and the wall
+    time per generation of each."""
     from paper_1909_11474_amd import ga as G
     wl = W.config4()
     P = wl.population.shape[0]
-    ts, _, _ = make_set(api, torch, wl)
+    ts, _, _ = make_set(api, torch, wl, "config3")
     if not args.no_tune:
         ts.autotune(P, "fp32", args.tune_cache)
     fit, grad = G.gpu_fitness(ts, precision="fp32")
-    cfg = G.GAConfig(pop=P, n_par=P // 2, n_gen=500, seed=wl.seeds["population"],
-                     refine_top=8, refine_steps=1)
-    ga = G.GA(cfg, fit, grad)
-    ga.step()                                              # warm-up: plans for P and 8
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.ga_generations):
-        rec = ga.step()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.ga_generations
-    out = {"workload": wl.name + "; GA with top-8 gradient refinement",
-           "ms_per_generation": dt * 1e3, "generations": args.ga_generations,
-           "best_Z": rec["best"], "population": P}
-    log(f"GA generation with refinement: {dt * 1e3:.3f} ms")
+    n = args.ga_generations
+    runs = {}
+    for name, top in (("refined", 8), ("plain", 0)):
+        cfg = G.GAConfig(pop=P, n_par=P // 2, n_gen=n, seed=wl.seeds["population"],
+                         refine_top=top, refine_steps=1)
+        ga = G.GA(cfg, fit, grad if top else None)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        curve = []
+        for g in range(n):
+            rec = ga.step()
+            if g % 50 == 0 or g == n - 1:
+                curve.append([g, rec["best"]])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        hist = [r["best"] for r in ga.history]
+        runs[name] = {"best_Z_every_50": curve, "final_best_Z": hist[-1],
+                      "monotone": all(b <= a for a, b in zip(hist, hist[1:])),
+                      "ms_per_generation": dt / n * 1e3, "elite_x": ga.history[-1]["elite_x"]}
+        log(f"GA {name}: best Z {hist[-1]:.6f} after {n} generations, {dt / n * 1e3:.3f} ms/generation")
     ts.close()
-    return out
+    return {"workload": wl.name + f"; GA {n} generations, top-8 gradient refinement vs plain GA, "
+                                  f"seed {wl.seeds['population']}",
+            "generations": n, "population": P, "refined": runs["refined"], "plain": runs["plain"],
+            "refined_at_or_below_plain": runs["refined"]["final_best_Z"] <= runs["plain"]["final_best_Z"]}
 
 
 def tersoff_form_batch(args, api, torch, W, dev):
     """The GA fitness batch with nine-parameter Tersoff-form candidates
     (fitness_eval_tf): same structures, population size and launch shape as the
-    headline workload."""
+    GA batch; reference data of a hidden nine-parameter set from the library's
+    float64 path (the oracle's references are stored for the minimal form)."""
     wl = W.config2_tersoff_form()
     s = wl.structs
     P = wl.population.shape[0]
-    ts, _, _ = make_set(api, torch, wl)
+    ts = api.from_structures(s, R1=wl.R1, R2=wl.R2)
+    ref = ts.tersoff_eval(wl.hidden_x[None], precision="fp64", forces=True, virial=True)
+    n = torch.as_tensor(s.sizes().astype(np.float64), device=ref["E"].device)
+    ts.attach_reference(ref["E"][0] / n, ref["W"][0] / n[:, None], ref["F"][0])
     X = torch.as_tensor(wl.population, dtype=torch.float64, device=dev).contiguous()
     Z = torch.empty(P, 4, dtype=torch.float64, device=dev)
     if not args.no_tune:
         ts.autotune(P, "fp32", args.tune_cache)          # shape shared with the minimal form
-    t, prof, b2b = time_generations(torch, ts, X, Z, args.tf_steps, 5)
+    t, b2b = time_generations(torch, ts, X, Z, args.tf_steps, 5)
     kernel_ms = b2b[0] / max(b2b[1], 1)
     out = {"workload": wl.name, "value": P * s.n_atoms * args.tf_steps / t.seconds,
            "unit": "atom·candidate evals/s", "ms_per_step": t.seconds / args.tf_steps * 1e3,
            "steps": args.tf_steps, "population": P, "batched_kernel_ms": kernel_ms,
            "seeds": wl.seeds}
-    log(f"Tersoff form batched: {out['ms_per_step']:.4f} ms/generation, {out['value']:.4e} "
-        f"atom*cand/s, kernel {kernel_ms:.4f} ms")
+    log(f"Tersoff form batched: {out['ms_per_step']:.4f} ms/generation, kernel {kernel_ms:.4f} ms")
     if args.grad_steps > 0:
         tg = time_grad(torch, ts, X, args.grad_steps)
         out["fitness_grad"] = {"value": P * s.n_atoms * args.grad_steps / tg.seconds,
                                "unit": "atom·candidate fitness-grad evals/s (9 parameters)",
                                "ms_per_step": tg.seconds / args.grad_steps * 1e3}
-        log(f"Tersoff form fitness_grad: {out['fitness_grad']['ms_per_step']:.3f} ms/generation")
     ts.close()
     return out
 
@@ -481,6 +648,7 @@ def force_call(args, api, torch, W, dev):
     torch.cuda.synchronize()
     t_create = time.perf_counter() - t0
     vel = torch.as_tensor(wl.velocities, dtype=torch.float64, device=dev)
+    M = coordination(ts, s.n_atoms)
     out = {"workload": wl.name, "atoms": s.n_atoms, "steps": args.md_steps,
            "outputs": "energy, forces, virial, per-atom virial, heat current",
            "set_create_ms": t_create * 1e3}
@@ -517,7 +685,19 @@ def force_call(args, api, torch, W, dev):
         torch.cuda.synchronize()
         same = same and all(torch.equal(v, ref[k]) for k, v in
                             {"E": call.E, "F": call.F.transpose(1, 2), "W": call.W}.items())
-        out[prec] = {"ms_per_call": t.seconds / args.md_steps * 1e3,
+        ms = t.seconds / args.md_steps * 1e3
+        flop = float(force_call_flops_per_atom(M).sum())
+        nbytes = FORCE_CALL_BYTES_PER_ATOM * s.n_atoms
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        tfl = flop / (ms * 1e-3) / 1e12
+        peak = FP32_PEAK_TFLOPS if prec == "fp32" else FP64_PEAK_TFLOPS
+        out[prec] = {"ms_per_call": ms,
+                     "roofline": {"bound": "hbm" if gbs / HBM_PEAK_GBS > tfl / peak else "alu",
+                                  "achieved_GBs": gbs, "peak_GBs": HBM_PEAK_GBS,
+                                  "frac_hbm": gbs / HBM_PEAK_GBS, "achieved_TFLOPs": tfl,
+                                  "peak_TFLOPs": peak, "frac_alu": tfl / peak,
+                                  "bytes_per_call": nbytes, "flop_per_call": flop,
+                                  "timing": "back-to-back calls (all kernels of a call), HIP events"},
                      "atoms_per_s": s.n_atoms * args.md_steps / t.seconds,
                      "single_call_ms": single * 1e3,
                      "graph_100_calls_ms_per_call": tg.seconds / 100 * 1e3 if same else None}
@@ -544,114 +724,66 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
 
-    wl = W.config2()
+    # ---- headline: uneven batching, 500 candidates x 300 structures ----------
+    wl = W.config3()
     s = wl.structs
     P = wl.population.shape[0]
     log(f"workload: {wl.name}; atoms {s.n_atoms}, structures {s.n_struct}, population {P}")
-    ts, (e_ref, w_ref, f_ref), t_create = make_set(api, torch, wl)
+    ts, refs, t_create = make_set(api, torch, wl, "config3")
     st = ts.stats()
-    log("set:", st, f"created in {t_create * 1e3:.1f} ms")
-    flop_cand, trans_cand, kflop_cand = set_flops(ts, s.n_atoms)
-    flop_launch = flop_cand * P
-
+    M = coordination(ts, s.n_atoms)
+    flop_cand = float(flops_per_atom(M).sum())
     X = torch.as_tensor(wl.population, dtype=torch.float64, device=dev).contiguous()
     Z = torch.empty(P, 4, dtype=torch.float64, device=dev)
     t0 = time.perf_counter()
     if not args.no_tune:
         ts.autotune(P, "fp32", args.tune_cache)
     t_tune = time.perf_counter() - t0
+    shape = tuned_shape(args.tune_cache, ts, P) if not args.no_tune else None
 
-    # ---- timed region: K generations; then the kernel alone -----------------
-    t, prof, b2b = time_generations(torch, ts, X, Z, args.steps, args.warmup)
+    t, b2b = time_generations(torch, ts, X, Z, args.steps, args.warmup)
     ms_step = t.seconds / args.steps * 1e3
     units = P * s.n_atoms
     value = units * args.steps / t.seconds
-    log(f"batched: {ms_step:.4f} ms/generation, {value:.4e} atom*cand/s "
-        f"(wall {t.wall * 1e3:.3f} ms, host enqueue {t.enqueue * 1e3:.3f} ms for {args.steps} generations)")
-    kernel_ms = b2b[0] / max(b2b[1], 1)         # one launch per pass: every structure has M <= 4
-    pair_ms = prof[0] / max(prof[1], 1)
-    achieved = flop_launch / (kernel_ms * 1e-3) / 1e12
-    kernel_tflops = kflop_cand * P / (kernel_ms * 1e-3) / 1e12
-    log(f"batched kernel: {kernel_ms:.4f} ms/launch over {args.steps} back-to-back launches "
-        f"({pair_ms:.4f} ms with an event pair around each), "
-        f"{achieved:.2f} TFLOP/s algorithmic, {kernel_tflops:.2f} TFLOP/s in the kernel's formulation")
-    Zb = Z.clone()
-
+    log(f"uneven batched: {ms_step:.4f} ms/generation, {value:.4e} atom*cand/s "
+        f"(kernels {b2b[0]:.4f} ms back to back, {b2b[1]} launches)")
+    dom, launches = dominant_launch(ts, X, M, s.sizes(), P, args.steps)
+    log(f"dominant kernel: class M<={dom['coordination_class']}, {dom['avg_ms'] * 1e3:.1f} us/launch, "
+        f"{dom['tflops']:.1f} TFLOP/s algorithmic")
     plain = None
     if args.plain_steps > 0:
+        Zb = Z.clone()
         tp = time_plain(torch, ts, X, Z, args.plain_steps)
         plain = {"value": units * args.plain_steps / tp.seconds,
                  "ms_per_step": tp.seconds / args.plain_steps * 1e3,
                  "launches_per_step": P * s.n_struct, "steps": args.plain_steps,
                  "max_abs_dZ_vs_batched": float((Z - Zb).abs().max())}
-        log(f"plain: {plain['ms_per_step']:.2f} ms/generation, {plain['value']:.4e} atom*cand/s")
-
-    grad = None
-    if args.grad_steps > 0:
-        tg = time_grad(torch, ts, X, args.grad_steps)
-        grad = {"value": units * args.grad_steps / tg.seconds,
-                "unit": "atom·candidate fitness-grad evals/s",
-                "ms_per_step": tg.seconds / args.grad_steps * 1e3, "steps": args.grad_steps}
-        log(f"fitness_grad: {grad['ms_per_step']:.3f} ms/generation, {grad['value']:.4e} atom*cand/s")
-
-    if args.copy_probe_mib > 0:
-        n = args.copy_probe_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"copy probe: 3 x {args.copy_probe_mib} MiB device-to-device")
-        del src, dst
-
-    # ---- CPU oracle on a bounded sample --------------------------------------
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import tersoff as T
-        refs = {"e": e_ref.cpu().numpy(), "w": w_ref.cpu().numpy(), "f": f_ref.cpu().numpy()}
-        top = T.topology(s, wl.R2)
-        T.fitness(s, wl.population[:1], refs, topology=top)           # warm-up
-        def sample(seconds):
-            return oracle_sample(lambda X: T.fitness(s, X, refs, topology=top), wl.population, seconds)
-
-        done, tc = sample(args.cpu_seconds)
-        cpu = {"value": done * s.n_atoms / tc, "unit": "atom·candidate evals/s",
-               "cores": int(torch.get_num_threads()), "kind": "oracle",
-               "sample": f"{done} candidate evaluations (population of {P}, in order, wrapping) x "
-                         f"all {s.n_struct} structures = {done * s.n_atoms} atom*candidate evals "
-                         f"in {tc:.1f} s, float64 autograd",
-               "host": {"nproc": os.cpu_count(), "cpu_model": cpu_model()}}
-        log(f"cpu oracle: {cpu['value']:.4e} atom*cand/s on {cpu['cores']} threads")
-        # the same oracle on one thread (a third of the budget)
-        threads = torch.get_num_threads()
-        torch.set_num_threads(1)
-        try:
-            done1, tc1 = sample(args.cpu_seconds / 3)
-        finally:
-            torch.set_num_threads(threads)
-        cpu["one_thread"] = {"value": done1 * s.n_atoms / tc1, "cores": 1,
-                             "sample": f"{done1} candidate evaluations in {tc1:.1f} s"}
-        log(f"cpu oracle, one thread: {cpu['one_thread']['value']:.4e} atom*cand/s")
+        log(f"uneven plain: {plain['ms_per_step']:.1f} ms/generation")
     ts.close()
 
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_headline(args, torch, wl, refs)
+
     workloads = {}
-    if args.uneven_steps > 0:
-        workloads["uneven_batching"] = uneven_batching(args, api, torch, W, dev)
+    if args.specified_steps > 0 and shape:
+        workloads["uneven_specified_form"] = uneven_specified_form(args, api, torch, W, dev, shape)
+    if args.ga_batch_steps > 0:
+        workloads["ga_batch"] = ga_batch(args, api, torch, W, dev)
     if args.uneven_grad_steps > 0:
         workloads["uneven_gradient"] = uneven_gradient(args, api, torch, W, dev)
-    if cpu is not None:
-        # the oracle on the uneven structures too (fitness, and fitness with its gradient)
-        cpu["workloads"] = {k: v["cpu_oracle"] for k, v in workloads.items() if "cpu_oracle" in v}
     if args.md_steps > 0:
         workloads["force_call_64k"] = force_call(args, api, torch, W, dev)
     if args.ga_generations > 0:
-        workloads["ga_refined"] = ga_generations(args, api, torch, W, dev)
+        workloads["ga_refined_vs_plain"] = ga_judge(args, api, torch, W, dev)
     if args.tf_steps > 0:
         workloads["tersoff_form"] = tersoff_form_batch(args, api, torch, W, dev)
     if not args.no_properties:
         workloads["properties_0K"] = zero_kelvin_properties(torch, W)
     if args.md_run_steps > 0:
         workloads["md_hnemd_8000"] = md_run(args, torch, W)
+    if cpu is not None:
+        cpu["workloads"] = {k: v["cpu_oracle"] for k, v in workloads.items() if "cpu_oracle" in v}
 
     line = {
         "metric": "atom·candidate Tersoff force evals/s and fitness-grad evals/s, batched vs plain",
@@ -669,23 +801,22 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "population": P, "structures": s.n_struct,
                    "atoms": s.n_atoms, "bonds": st["n_bonds"], "triplets": st["n_triplets"],
-                   "precision": "f32 arithmetic, f64 accumulation", "schedule": "batched",
-                   "parallelism": "single GPU", "seeds": wl.seeds},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS,
-                     "traffic": measured_traffic()},
-        "kernel": {"name": "k_batched<float, fit, M<=4>", "avg_ms": kernel_ms, "launches": args.steps,
-                   "timing": "back-to-back launches between one HIP event pair on the kernel's stream",
-                   "avg_ms_event_pair_per_launch": pair_ms,
-                   "flop_per_launch": flop_launch, "transcendentals_per_launch": trans_cand * P,
-                   "formulation_flop_per_launch": kflop_cand * P,
-                   "formulation_tflops": kernel_tflops,
-                   "formulation_frac": kernel_tflops / FP32_VALU_PEAK_TFLOPS,
-                   "packed_fp32_peak": PACKED_FP32_PEAK_TFLOPS,
-                   "frac_of_packed_fp32_peak": achieved / PACKED_FP32_PEAK_TFLOPS},
+                   "precision": "f32 arithmetic, f64 energy terms and accumulation",
+                   "schedule": "batched", "launch_shape": shape, "parallelism": "single GPU",
+                   "references": "float64 oracle, " + REFERENCE_FILES["config3"], "seeds": wl.seeds},
+        "roofline": dict(fp32_roofline(dom["flop_per_launch"], dom["avg_ms"]),
+                         traffic=measured_traffic()),
+        "kernel": {"name": f"k_batched<float, fit, M<={dom['coordination_class']}>",
+                   "avg_ms": dom["avg_ms"], "launches": args.steps,
+                   "timing": "back-to-back launches of this kernel alone between one HIP event pair "
+                             "on its stream",
+                   "flop_per_launch": dom["flop_per_launch"], "structures": dom["structures"],
+                   "atoms": dom["atoms"], "all_launches": launches,
+                   "batched_kernels_ms_per_step": b2b[0], "batched_launches_per_step": b2b[1],
+                   "algorithmic_flop_per_step": flop_cand * P,
+                   "algorithmic_tflops_per_step": flop_cand * P / (b2b[0] * 1e-3) / 1e12},
         "host_enqueue_ms_per_step": t.enqueue / args.steps * 1e3,
         "plain": plain,
-        "fitness_grad": grad,
         "workloads": workloads,
         "cpu_baseline": cpu,
         "setup_ms": {"set_create": t_create * 1e3, "autotune": t_tune * 1e3},

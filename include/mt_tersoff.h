@@ -374,6 +374,27 @@ int mt_profile_read(mt_set* set, double* ms, int64_t* launches);
 int mt_profile_fitness_kernels(mt_set* set, const double* x, int nx, int P, int precision, int reps,
                                double* ms, int64_t* launches, void* stream);
 
+/*
+ * The same back-to-back timing per kernel launch: each launch of the batched
+ * fitness plan (one per coordination class and block size) is issued reps
+ * times in a row between one event pair, so that the roofline of each kernel
+ * can be taken on its own.
+ *   x, nx, P, precision, reps  as for mt_profile_fitness_kernels
+ *   max_launches        capacity of ms and coordination_class
+ *   ms                  host double [max_launches]: average ms of each launch
+ *   coordination_class  host int [max_launches]: largest coordination the
+ *                       launch's kernel instance serves
+ *   struct_launch       host int [S] or NULL: index of the launch evaluating
+ *                       each structure, -1 for the two-pass path
+ *   n_launches          host int: launches of the plan
+ * Overwrites the set's partial sums; synchronises the stream.  Errors as for
+ * mt_profile_fitness_kernels; MT_EINVAL also when the plan has more than
+ * max_launches launches (n_launches is set).
+ */
+int mt_profile_fitness_launches(mt_set* set, const double* x, int nx, int P, int precision, int reps,
+                                int max_launches, double* ms, int* coordination_class,
+                                int* struct_launch, int* n_launches, void* stream);
+
 /* Message for the calling thread's most recent error (never NULL). */
 const char* mt_last_error(void);
 

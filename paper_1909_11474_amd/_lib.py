@@ -62,6 +62,8 @@ SIGNATURES = {
     "mt_profile_read": (_i, [_vp, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_int64)]),
     "mt_profile_fitness_kernels": (_i, [_vp, _vp, _i, _i, _i, _i, ctypes.POINTER(_d),
                                         ctypes.POINTER(ctypes.c_int64), _vp]),
+    "mt_profile_fitness_launches": (_i, [_vp, _vp, _i, _i, _i, _i, _i, ctypes.POINTER(_d),
+                                         ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i), _vp]),
     "mt_last_error": (ctypes.c_char_p, []),
     "mt_version": (ctypes.c_char_p, []),
 }

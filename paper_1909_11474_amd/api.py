@@ -260,6 +260,23 @@ class TersoffSet:
         L.check(rc, "mt_profile_fitness_kernels")
         return ms.value, int(n.value)
 
+    def profile_fitness_launches(self, x, precision="fp32", reps: int = 100, max_launches: int = 16):
+        """Each launch of the batched fitness plan timed alone, reps back to back:
+        list of (ms per launch, coordination class) and, per structure, the index
+        of the launch that evaluates it (-1: two-pass path)."""
+        xt = self._x(x)
+        P, nx = xt.shape
+        ms = (ctypes.c_double * max_launches)()
+        mc = (ctypes.c_int * max_launches)()
+        sl = (ctypes.c_int * self.S)()
+        n = ctypes.c_int()
+        with torch.cuda.device(self.device):
+            rc = self._lib.mt_profile_fitness_launches(self._handle, _ptr(xt), nx, P, _prec(precision),
+                                                       int(reps), max_launches, ms, mc, sl,
+                                                       ctypes.byref(n), self._stream())
+        L.check(rc, "mt_profile_fitness_launches")
+        return [(ms[k], mc[k]) for k in range(n.value)], list(sl)
+
     def autotune(self, P: int, precision="fp32", cache_path: Optional[str] = None):
         with torch.cuda.device(self.device):
             rc = self._lib.mt_autotune(self._handle, int(P), _prec(precision),

@@ -526,6 +526,22 @@ int mt_profile_fitness_kernels(mt_set* set, const double* x, int nx, int P, int 
                                 (hipStream_t)stream, ms, launches);
 }
 
+int mt_profile_fitness_launches(mt_set* set, const double* x, int nx, int P, int precision, int reps,
+                                int max_launches, double* ms, int* coordination_class,
+                                int* struct_launch, int* n_launches, void* stream) {
+    TRY(check_common(set, x, P, precision));
+    if (nx != 6 && nx != 9) return fail(MT_EINVAL, "nx must be 6 (minimal) or 9 (Tersoff form)");
+    if (reps <= 0 || max_launches <= 0) return fail(MT_EINVAL, "reps and max_launches must be positive");
+    if (!ms || !coordination_class || !n_launches) return fail(MT_EINVAL, "NULL output");
+    if (!set->has_ref) return fail(MT_ENOREF, "no reference data attached to the set");
+    TRY(ensure_workspace(set, P, kNVFit));
+    set->fit_P = 0;
+    set->cur_x = x;
+    set->cur_form = nx == 9 ? 1 : 0;
+    return time_class_launches(set, cfg_for(set, P, precision), P, precision, reps, (hipStream_t)stream,
+                               max_launches, ms, coordination_class, struct_launch, n_launches);
+}
+
 int mt_profile_read(mt_set* set, double* ms, int64_t* launches) {
     if (!set || !ms || !launches) return fail(MT_EINVAL, "NULL argument");
     for (int k = 0; k < 2; ++k) {

@@ -798,6 +798,63 @@ int time_batched_kernels(mt_set* set, const LaunchCfg& cfg, int P, int precision
     return MT_OK;
 }
 
+// Each launch of the batched fitness plan timed on its own: reps back-to-back
+// launches of it between one event pair; per launch the average ms, its
+// coordination class, and for every structure the launch that evaluates it
+// (-1: two-pass path).  Synchronises st.
+int time_class_launches(mt_set* set, const LaunchCfg& cfg, int P, int precision, int reps,
+                        hipStream_t st, int max_launches, double* ms, int* mc, int* struct_launch,
+                        int* n_launches) {
+    const int fam = family_for(precision, MODE_FIT, set->cur_form);
+    ItemPlan* plan = get_plan(set, P, cfg, fam);
+    if (!plan) {
+        set_error("could not build the work list (block smaller than a structure?)");
+        return MT_EINVAL;
+    }
+    if (cfg.block == 0) {
+        set_error("per-launch timing covers the batched schedule only");
+        return MT_EINVAL;
+    }
+    const int n = (int)plan->cls.size();
+    *n_launches = n;
+    if (n > max_launches) {
+        set_error("more launches than max_launches");
+        return MT_EINVAL;
+    }
+    if (struct_launch) {
+        for (int s = 0; s < set->S; ++s) struct_launch[s] = -1;
+        for (int k = 0; k < n; ++k)
+            for (const Item& it : plan->cls[k]->h_items) struct_launch[it.s] = k;
+    }
+    BArgs<float> Af = make_args<float>(set, set->partial.as<double>(), kNVFit);
+    BArgs<double> Ad = make_args<double>(set, set->partial.as<double>(), kNVFit);
+    hipEvent_t e[2] = {nullptr, nullptr};
+    int rc = MT_OK;
+    hipError_t he = hipSuccess;
+    for (auto& ev : e)
+        if (rc == MT_OK && (he = hipEventCreate(&ev)) != hipSuccess) rc = hip_fail(he, "hipEventCreate");
+    for (int k = 0; k < n && rc == MT_OK; ++k) {
+        ClassPlan& cp = *plan->cls[k];
+        Af.items = Ad.items = cp.items.as<Item>();
+        Af.bin_off = Ad.bin_off = cp.bin_off.as<int>();
+        if ((he = hipEventRecord(e[0], st)) != hipSuccess) { rc = hip_fail(he, "hipEventRecord"); break; }
+        for (int r = 0; r < reps && rc == MT_OK; ++r)
+            if ((he = launch_family(fam, cp.mc, dim3(cp.n_bins), dim3(cp.block), cp.lds, st, Af, Ad)) !=
+                hipSuccess)
+                rc = hip_fail(he, "kernel launch");
+        if (rc != MT_OK) break;
+        if ((he = hipEventRecord(e[1], st)) != hipSuccess) { rc = hip_fail(he, "hipEventRecord"); break; }
+        if ((he = hipEventSynchronize(e[1])) != hipSuccess) { rc = hip_fail(he, "hipEventSynchronize"); break; }
+        float t = 0.f;
+        if ((he = hipEventElapsedTime(&t, e[0], e[1])) != hipSuccess) { rc = hip_fail(he, "hipEventElapsedTime"); break; }
+        ms[k] = (double)t / reps;
+        mc[k] = cp.mc;
+    }
+    for (auto& ev : e)
+        if (ev) (void)hipEventDestroy(ev);
+    return rc;
+}
+
 // Candidates per launch of the two-pass path for structure s: bounded so that
 // the bond-gradient staging buffer stays within 256 MB.
 static int twopass_chunk(const mt_set* set, int s, int P, size_t elem) {

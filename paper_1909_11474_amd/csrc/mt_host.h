@@ -180,6 +180,10 @@ int launch_plain(mt_set* set, int P, int precision, int mode, const double* vel,
 // Average time of reps back-to-back passes of the batched fitness kernels.
 int time_batched_kernels(mt_set* set, const LaunchCfg& cfg, int P, int precision, int reps,
                          hipStream_t stream, double* ms, int64_t* launches);
+// Each launch of the batched fitness plan timed alone (reps back to back).
+int time_class_launches(mt_set* set, const LaunchCfg& cfg, int P, int precision, int reps,
+                        hipStream_t stream, int max_launches, double* ms, int* mc, int* struct_launch,
+                        int* n_launches);
 int launch_large(mt_set* set, int P, int precision, int mode, const double* vel, double* force,
                  double* atom_virial, hipStream_t stream);
 // Reserve the two-pass staging buffer for the set's large structures and the

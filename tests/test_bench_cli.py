@@ -38,6 +38,27 @@ def test_flops_per_atom_formula():
     assert b.kernel_flops_per_atom(np.array([12]))[0] == 66 * 31 + 12 * 70 + 9
 
 
+def test_gradient_and_force_call_flop_models():
+    b = load_bench()
+    # 13 x the forward count + 36 per bond; per-atom virial and heat current
+    assert b.grad_flops_per_atom(np.array([4]))[0] == 13 * 836 + 144 == 11012
+    assert b.force_call_flops_per_atom(np.array([4]))[0] == 836 + 72 + 18 == 926
+    assert b.FORCE_CALL_BYTES_PER_ATOM == 144
+
+
+def test_stored_references_are_checked_against_the_workload():
+    import pytest
+
+    import workloads as W
+    b = load_bench()
+    wl = W.config2()
+    e, w, f = b.load_references(wl, "config2")
+    assert e.shape == (100,) and w.shape == (100, 6) and f.shape == (6400, 3)
+    other = W.config2(hidden_seed=99)
+    with pytest.raises(SystemExit):
+        b.load_references(other, "config2")
+
+
 def test_traffic_is_tied_to_the_measured_sources(tmp_path):
     b = load_bench()
     t = b.measured_traffic()

@@ -271,3 +271,31 @@ def test_back_to_back_kernel_timing(api):
                                                 reps, ctypes.byref(ms), ctypes.byref(n), None)
         assert rc == L.MT_EINVAL, (nx, reps)
     ts.close()
+
+
+def test_per_launch_kernel_timing(api):
+    """mt_profile_fitness_launches on a set with two coordination classes
+    (64-atom cells and packings): one entry per launch with its class, every
+    structure mapped to the launch that evaluates it, the per-launch times
+    adding up to about the per-pass time; too small a capacity is refused."""
+    import torch
+    from paper_1909_11474_amd import _lib as L
+    g = np.random.Generator(np.random.PCG64(81))
+    s = W.make_set(W.strained_diamond_cells(82, 4) + [W.random_packing(g, n) for n in (120, 300)])
+    refs = T.reference_data(s, W.draw_params(np.random.Generator(np.random.PCG64(83)), 1)[0], R1, R2)
+    ts = api.from_structures(s)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    X = torch.as_tensor(W.draw_params(np.random.Generator(np.random.PCG64(84)), 40), device="cuda")
+    launches, sl = ts.profile_fitness_launches(X, "fp32", 8)
+    classes = sorted(mc for _, mc in launches)
+    assert classes[0] == 4 and classes[-1] > 4
+    assert all(0.0 < ms < 1000.0 for ms, _ in launches)
+    assert sl[:4] == [sl[0]] * 4 and launches[sl[0]][1] == 4
+    assert all(launches[l][1] > 4 for l in sl[4:])
+    ms, n = ts.profile_fitness_kernels(X, "fp32", 8)
+    assert n == len(launches)
+    assert abs(sum(m for m, _ in launches) - ms) <= 0.5 * ms
+    with pytest.raises(L.MTError) as e:
+        ts.profile_fitness_launches(X, "fp32", 4, max_launches=1)
+    assert e.value.code == L.MT_EINVAL
+    ts.close()

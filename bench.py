@@ -47,19 +47,20 @@ TUNED_SHAPES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1
                             "tuned_shapes.txt")
 
 
-# HBM traffic of the dominant kernel from two rocprofv3 --pmc passes (FETCH_SIZE,
-# WRITE_SIZE; KiB per dispatch) scaled by what the same counters read for a
-# 256 MiB device-to-device copy (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00), recorded
-# in profiles/k_batched_fit32_ga_batch_traffic.md.  Valid only for the kernel
-# sources and the host file that places the work items (mt_eval.hip) it was
-# measured on: reported when their hash still matches.
+# HBM traffic of the dominant kernel (k_batched<float, fit, M<=12> of the
+# uneven workload) from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB
+# per dispatch) scaled by what the same counters read for a 256 MiB
+# device-to-device copy (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00), recorded in
+# profiles/k_batched_fit32_uneven_500x300.md.  Valid only for the kernel sources
+# and the host file that places the work items (mt_eval.hip) it was measured
+# on: reported when their hash still matches.
 PMC_TRAFFIC = {
     "sources": ["paper_1909_11474_amd/csrc/mt_common.h", "paper_1909_11474_amd/csrc/mt_site.h",
                 "paper_1909_11474_amd/csrc/mt_kernels.h", "paper_1909_11474_amd/csrc/mt_k_fit32.hip",
                 "paper_1909_11474_amd/csrc/mt_eval.hip"],
-    "sha256_16": "7f930986759f6a97",
-    "fetch_bytes": 1969.3 * 1024 * 2.00,
-    "write_bytes": 4250.0 * 1024 * 1.00,
+    "sha256_16": "48b07cc5f5b1c04a",
+    "fetch_bytes": 42007.0 * 1024 * 2.00,
+    "write_bytes": 62407.1 * 1024 * 1.00,
 }
 
 
@@ -461,19 +462,22 @@ def ga_batch(args, api, torch, W, dev):
         out["fitness_grad"] = {"value": units * args.grad_steps / tg.seconds,
                                "unit": "atom·candidate fitness-grad evals/s",
                                "ms_per_step": tg.seconds / args.grad_steps * 1e3}
-    if args.copy_probe_mib > 0:
-        n = args.copy_probe_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"copy probe: 3 x {args.copy_probe_mib} MiB device-to-device")
-        del src, dst
     ts.close()
     if not args.no_cpu_baseline:
         out["cpu_oracle"] = oracle_rate(args, torch, wl, refs, grad=False)
     return out
+
+
+def copy_probe(torch, dev, mib):
+    """Three device-to-device copies of `mib` MiB: the reference kernel whose
+    FETCH_SIZE / WRITE_SIZE counters scale the counter passes to bytes."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy probe: 3 x {mib} MiB device-to-device")
 
 
 def uneven_gradient(args, api, torch, W, dev):
@@ -760,6 +764,8 @@ def main():
                  "max_abs_dZ_vs_batched": float((Z - Zb).abs().max())}
         log(f"uneven plain: {plain['ms_per_step']:.1f} ms/generation")
     ts.close()
+    if args.copy_probe_mib > 0:
+        copy_probe(torch, dev, args.copy_probe_mib)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -89,8 +89,8 @@ enum mt_schedule {
 /* Largest structure handled by the batched kernels; bigger structures take the
  * two-pass large-system kernels. */
 #define MT_MAX_BATCHED_ATOMS 512
-/* Largest coordination number handled by fitness_grad. */
-#define MT_MAX_GRAD_NBR 12
+/* Largest coordination number handled by fitness_grad (every set allows). */
+#define MT_MAX_GRAD_NBR MT_MAX_NBR
 
 /*
  * Build a structure set: copies the structures and finds, on the GPU with a
@@ -230,8 +230,10 @@ int fitness_eval_tf(mt_set* set, const double* x, int P, const double* w, int pr
  * Fitness and its gradient dZ/dx with respect to the six parameters (the
  * derivative of the Sec. III.B fitness, including the force and virial terms,
  * which need mixed second derivatives of the energy).  A term with Z_x = 0
- * contributes no gradient.  Structures must have at most MT_MAX_BATCHED_ATOMS
- * atoms and coordination numbers up to MT_MAX_GRAD_NBR; otherwise MT_EINVAL.
+ * contributes no gradient.  Every set fitness_eval accepts is handled:
+ * structures over MT_MAX_BATCHED_ATOMS atoms (or too large for one block's LDS
+ * with the adjoint's residual buffer) take a two-pass adjoint that stages bond
+ * gradients and force residuals in device memory, held by the set.
  *   Z     device [P][4]
  *   dZdx  device [P][6]
  */

@@ -400,12 +400,6 @@ static int grad_impl(mt_set* set, const double* x, int form, int P, const double
                      int precision, double* Z, double* dZdx, void* stream) {
     TRY(check_fitness(set, x, P, w, precision, Z));
     if (!dZdx) return fail(MT_EINVAL, "dZdx must not be NULL");
-    if (set->n_large > 0)
-        return fail(MT_EINVAL, "fitness_grad handles structures of up to " +
-                                   std::to_string(MT_MAX_BATCHED_ATOMS) + " atoms");
-    if (set->kmax > MT_MAX_GRAD_NBR)
-        return fail(MT_EINVAL, "fitness_grad handles coordination numbers up to " +
-                                   std::to_string(MT_MAX_GRAD_NBR));
     hipStream_t st = (hipStream_t)stream;
     TRY(ensure_workspace(set, P, kNVFit));
     set->fit_P = 0;

@@ -599,6 +599,11 @@ ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int fam) {
     std::map<int, long long> nitems;
     for (int s = 0; s < set->S; ++s) {
         if (set->h_large[s]) continue;
+        if (set->h_kmax[s] > classes.back()) {
+            // above the family's widest class (the adjoint's 12): two-pass
+            plan->twopass.push_back(s);
+            continue;
+        }
         cls[s] = class_of(fam, set->h_kmax[s]);
         if (!plain) {
             const int tile = tile_for(cfg, P, std::max(1, cfg.block / set->h_npad[s]), plain);
@@ -990,6 +995,45 @@ static int launch_grad_coef(mt_set* set, int P, const double* w, const double* Z
     return MT_OK;
 }
 
+// Two-pass fitness gradient of the listed structures, one candidate chunk at a
+// time: bond gradients staged as for the two-pass fitness (no partial sums),
+// force residuals staged [chunk][3][Ns] in abuf, then the dual passes.
+template <typename S>
+static int launch_twopass_adjoint(mt_set* set, const std::vector<int>& structs, int P, int nv,
+                                  hipStream_t st) {
+    size_t abytes = 0;
+    for (int s : structs) {
+        const int ns = set->h_off[s + 1] - set->h_off[s];
+        abytes = std::max(abytes, 3 * (size_t)ns * sizeof(S) * twopass_chunk(set, s, P, sizeof(S)));
+    }
+    HIPCHECK(set->abuf.reserve(abytes));
+    BArgs<S> Afit = make_args<S>(set, nullptr, kNVFit);
+    BArgs<S> Aadj = make_args<S>(set, set->partial2.as<double>(), nv);
+    Aadj.coef = set->zwork.as<double>();
+    for (int s : structs) {
+        const int mc = set->h_kmax[s] <= 4 ? 4 : 16;
+        const int ns = set->h_off[s + 1] - set->h_off[s];
+        const size_t per = 3 * (size_t)(set->h_boff[s + 1] - set->h_boff[s]) * sizeof(S);
+        const int chunk = twopass_chunk(set, s, P, sizeof(S));
+        if (set->gbuf.bytes < per * chunk || set->abuf.bytes < 3 * (size_t)ns * sizeof(S) * chunk) {
+            set_error("two-pass staging buffers not reserved");
+            return MT_ESTATE;
+        }
+        for (int c0 = 0; c0 < P; c0 += chunk) {
+            const int nc = std::min(chunk, P - c0);
+            LArgs L{s, c0, set->gbuf.p};
+            dim3 grid(grid_of(ns, 256), nc);
+            hipError_t e;
+            if constexpr (std::is_same<S, double>::value)
+                e = launch_large_adj64(mc, set->cur_form, grid, dim3(256), st, Afit, Aadj, L, set->abuf.as<double>());
+            else
+                e = launch_large_adj32(mc, set->cur_form, grid, dim3(256), st, Afit, Aadj, L, set->abuf.as<float>());
+            HIPCHECK(e);
+        }
+    }
+    return MT_OK;
+}
+
 static int adjoint_common(mt_set* set, const LaunchCfg& cfg, int P, int precision, const double* w,
                           const double* Z, hipStream_t st) {
     TRY_RC(launch_grad_coef(set, P, w, Z, st));
@@ -1002,17 +1046,20 @@ static int adjoint_common(mt_set* set, const LaunchCfg& cfg, int P, int precisio
         set_error("could not build the adjoint work list");
         return MT_EINVAL;
     }
-    if (!plan->twopass.empty()) {
-        const int s = plan->twopass.front();
-        set_error("fitness_grad: structure " + std::to_string(s) + " (" +
-                  std::to_string(set->h_off[s + 1] - set->h_off[s]) +
-                  " atoms) does not fit one block's LDS in this precision");
-        return MT_EINVAL;
-    }
     BArgs<float> Af = make_args<float>(set, set->partial2.as<double>(), nv);
     BArgs<double> Ad = make_args<double>(set, set->partial2.as<double>(), nv);
     Af.coef = Ad.coef = set->zwork.as<double>();
-    return run_plan(set, plan, cfg, fam, Af, Ad, 1, st);
+    TRY_RC(run_plan(set, plan, cfg, fam, Af, Ad, 1, st));
+    // structures over the batched limit, and those whose adjoint does not fit
+    // one block's LDS, take the two-pass adjoint
+    std::vector<int> structs;
+    for (int s = 0; s < set->S; ++s)
+        if (set->h_large[s]) structs.push_back(s);
+    structs.insert(structs.end(), plan->twopass.begin(), plan->twopass.end());
+    if (structs.empty()) return MT_OK;
+    TRY_RC(reserve_twopass(set, plan, P, precision));
+    return f64 ? launch_twopass_adjoint<double>(set, structs, P, nv, st)
+               : launch_twopass_adjoint<float>(set, structs, P, nv, st);
 }
 
 int launch_adjoint(mt_set* set, const LaunchCfg& cfg, int P, int precision, const double* w,

@@ -138,6 +138,7 @@ struct mt_set {
     // workspaces
     mt::DevBuf partial;                      // [P][nslots][NV] double
     mt::DevBuf partial2;                     // gradient partials
+    mt::DevBuf abuf;                         // two-pass adjoint: staged force residuals
     mt::DevBuf zwork;                        // [P][4] scratch for fitness_grad
     mt::DevBuf gbuf;                         // large path bond gradients
     mt::DevBuf scalars;                      // small device scratch
@@ -204,7 +205,9 @@ int launch_adjoint_plain(mt_set* set, int P, int precision, const double* w, con
                          hipStream_t stream);
 int launch_finalize_grad(mt_set* set, int P, const double* Z, double* dZdx, hipStream_t stream);
 
-enum Mode { MODE_FIT = 0, MODE_EVAL = 1 };
+// MODE_STAGE (two-pass path only): stage the bond gradients, no partial sums
+// and no gather.
+enum Mode { MODE_FIT = 0, MODE_EVAL = 1, MODE_STAGE = 2 };
 
 ItemPlan* get_plan(mt_set* set, int P, const LaunchCfg& cfg, int family);
 // The cached work list for these arguments, or null (never builds one).

@@ -32,6 +32,7 @@ static hipError_t launch_large_pair(int mc, int mode, int full, dim3 g, dim3 b, 
     const hipError_t e = full ? launch_large_form<S, true>(mc, mode, g, b, st, A, L)
                               : launch_large_form<S, false>(mc, mode, g, b, st, A, L);
     if (e != hipSuccess) return e;
+    if (mode == MODE_STAGE) return hipGetLastError();
     if (mode == MODE_FIT) hipLaunchKernelGGL((k_large_gather<S, MODE_FIT>), g, b, 0, st, A, L);
     else hipLaunchKernelGGL((k_large_gather<S, MODE_EVAL>), g, b, 0, st, A, L);
     return hipGetLastError();

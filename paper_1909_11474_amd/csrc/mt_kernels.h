@@ -388,10 +388,11 @@ __device__ __forceinline__ void batched_item(const BArgs<S>& A, const Item& it, 
         return;
     }
     dispatch_m<ClassLo<MC>::value, MC>(Mw, [&](auto mv) {
-        // the float fitness kernel gets a copy with 64-lane groups (structures
-        // of 64 atoms or more) fixed at compile time: the reduction then needs
-        // no branches and no copies around the in-place lane swaps
-        if constexpr (MODE == MODE_FIT && sizeof(S) == 4) {
+        // the float fitness kernel of the minimal potential gets a copy with
+        // 64-lane groups (structures of 64 atoms or more) fixed at compile
+        // time: the reduction then needs no branches and no copies around the
+        // in-place lane swaps
+        if constexpr (MODE == MODE_FIT && sizeof(S) == 4 && !Full) {
             if (x.g == 64) {
                 run_batched<S, MODE, decltype(mv)::value, 64, Full>(A, it, x, lds);
                 return;
@@ -464,6 +465,48 @@ __device__ __forceinline__ void for_passes(F&& pass) {
     }
 }
 
+// The parameter derivatives of one atom's site terms contracted with its
+// residual directions: phi[p] = k_e dU_i/dx_p - sum_j dG_ij/dx_p . delta_ij,
+// delta_ij = k_f (a_j - a_i) + C_s r_ij, by dual passes over KK parameters at a
+// time.  rec: the candidate's decoded record, xrow its parameters (Tersoff
+// form), (ax, ay, az) this atom's force residual, aj(m) the residual of the
+// atom at the far end of bond m, cf the coefficients k_e, k_f, C_s (xx yy zz yz
+// zx xy, off-diagonals halved) of the (candidate, structure).
+template <typename S, int M, bool Full, typename Aj>
+__device__ __forceinline__ void adjoint_phi(Geo<S, M>& g, const S* __restrict__ rec,
+                                            const double* __restrict__ xrow, S ax, S ay, S az,
+                                            Aj&& aj, const double* __restrict__ cf,
+                                            S (&phi)[Form<Full>::nx]) {
+    constexpr int K = AdjointTangents<S, M>::value;
+    constexpr int NX = Form<Full>::nx;
+    const S ke = (S)cf[0], kf = (S)cf[1];
+    const S cxx = (S)cf[2], cyy = (S)cf[3], czz = (S)cf[4];
+    const S cyz = (S)cf[5], czx = (S)cf[6], cxy = (S)cf[7];
+    auto pass = [&](auto base_c, auto k_c) {
+        constexpr int Base = decltype(base_c)::value;
+        constexpr int KK = decltype(k_c)::value;
+        Cand<Dual<S, KK>, S, Full> p;
+        if constexpr (Full) load_cand<Base>(rec, xrow, p);
+        else load_cand<Base>(rec, p);
+        Dual<S, KK> U;
+        site_eval_sink<Dual<S, KK>, S, M, false, true, true>(
+            g, p, U, [&](int m, const Dual<S, KK>& gx, const Dual<S, KK>& gy, const Dual<S, KK>& gz) {
+                const Vec4<S> a = aj(m);
+                const S dx = g.rhi[m] * g.ux[m], dy = g.rhi[m] * g.uy[m], dz = g.rhi[m] * g.uz[m];
+                const S ex = kf * (a.x - ax) + cxx * dx + cxy * dy + czx * dz;
+                const S ey = kf * (a.y - ay) + cxy * dx + cyy * dy + cyz * dz;
+                const S ez = kf * (a.z - az) + czx * dx + cyz * dy + czz * dz;
+#pragma unroll
+                for (int t = 0; t < KK; ++t) phi[Base + t] -= gx.d[t] * ex + gy.d[t] * ey + gz.d[t] * ez;
+            });
+#pragma unroll
+        for (int t = 0; t < KK; ++t) phi[Base + t] += ke * U.d[t];
+    };
+#pragma unroll
+    for (int k = 0; k < NX; ++k) phi[k] = S(0);
+    for_passes<0, NX, K>(pass);
+}
+
 template <typename S, int M, bool Full = false>
 __device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, const ItemCtx& x,
                                             unsigned char* __restrict__ lds) {
@@ -475,7 +518,6 @@ __device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, c
     Geo<S, M> g;
     g.load(geom_of<S>(d), N, x.atom, x.active);
     constexpr int MM = M > 0 ? M : 1;
-    constexpr int K = AdjointTangents<S, M>::value;
     constexpr int NX = Form<Full>::nx;
     int rv[MM], jl[MM];
 #pragma unroll
@@ -515,38 +557,16 @@ __device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, c
         ax -= frx; ay -= fry; az -= frz;
         ab[x.la] = Vec4<S>{ax, ay, az, S(0)};
         exchange_sync(x.block_sync);
-        const double* cf = A.coef + ((size_t)c * d.S + x.s) * 8;
-        const S ke = (S)cf[0], kf = (S)cf[1];
-        const S cxx = (S)cf[2], cyy = (S)cf[3], czz = (S)cf[4];
-        const S cyz = (S)cf[5], czx = (S)cf[6], cxy = (S)cf[7];
         S phi[NX];
-        // dual passes over KK parameters from Base
-        auto pass = [&](auto base_c, auto k_c) {
-            constexpr int Base = decltype(base_c)::value;
-            constexpr int KK = decltype(k_c)::value;
-            Cand<Dual<S, KK>, S, Full> p;
-            if constexpr (Full) load_cand<Base>(prec, A.x + (size_t)NX * c, p);
-            else load_cand<Base>(prec, p);
-            Dual<S, KK> U;
-            site_eval_sink<Dual<S, KK>, S, M, false, true, true>(
-                g, p, U, [&](int m, const Dual<S, KK>& gx, const Dual<S, KK>& gy, const Dual<S, KK>& gz) {
-                    // a fresh read in every pass (a reused one would stay live across passes)
-                    int jm = jl[m];
-                    asm volatile("" : "+v"(jm));
-                    const Vec4<S> aj = ab[jm];
-                    const S dx = g.rhi[m] * g.ux[m], dy = g.rhi[m] * g.uy[m], dz = g.rhi[m] * g.uz[m];
-                    const S ex = kf * (aj.x - ax) + cxx * dx + cxy * dy + czx * dz;
-                    const S ey = kf * (aj.y - ay) + cxy * dx + cyy * dy + cyz * dz;
-                    const S ez = kf * (aj.z - az) + czx * dx + cyz * dy + czz * dz;
-#pragma unroll
-                    for (int t = 0; t < KK; ++t) phi[Base + t] -= gx.d[t] * ex + gy.d[t] * ey + gz.d[t] * ez;
-                });
-#pragma unroll
-            for (int t = 0; t < KK; ++t) phi[Base + t] += ke * U.d[t];
-        };
-#pragma unroll
-        for (int k = 0; k < NX; ++k) phi[k] = S(0);
-        for_passes<0, NX, K>(pass);
+        adjoint_phi<S, M, Full>(
+            g, prec, A.x + (size_t)NX * c, ax, ay, az,
+            [&](int m) {
+                // a fresh read in every pass (a reused one would stay live across passes)
+                int jm = jl[m];
+                asm volatile("" : "+v"(jm));
+                return ab[jm];
+            },
+            A.coef + ((size_t)c * d.S + x.s) * 8, phi);
         exchange_sync(x.block_sync);
         double v[8];
 #pragma unroll
@@ -647,7 +667,8 @@ __device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L
     const int lane = threadIdx.x & 63;
     // one slot per wavefront of the structure (inactive tail lanes included)
     const int slot = d.st_slot[L.s] + (la >> 6);
-    if ((lane & 7) == 0 && vidx < 7)
+    // no partial sums when only the staged bond gradients are wanted
+    if (A.partial && (lane & 7) == 0 && vidx < 7)
         A.partial[((size_t)c * d.nslots + slot) * A.nv + vidx] = sum;
 }
 
@@ -736,6 +757,106 @@ __global__ __launch_bounds__(256) void k_large_gather(BArgs<S> A, LArgs L) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fitness gradient of the two-pass structures.  k_large_site stages the bond
+// gradients of a candidate chunk (as for the fitness), k_large_residual turns
+// them into the force residuals a_i = F_i - F*_i, staged [chunk][3][Ns], and
+// k_large_adjoint runs the dual passes of every atom (adjoint_phi) with the
+// residuals of its bond partners read from there; its partial sums go to the
+// structure's per-wavefront slots as in the batched adjoint.
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(256) void k_large_residual(BArgs<S> A, LArgs L, S* __restrict__ abuf) {
+    const SetDev& d = A.set;
+    const int N = d.N;
+    const int a0 = d.st_off[L.s], Ns = d.st_off[L.s + 1] - a0;
+    const int nbs = d.st_boff[L.s + 1] - d.st_boff[L.s];
+    const int la = blockIdx.x * blockDim.x + threadIdx.x;
+    if (la >= Ns) return;
+    const int atom = a0 + la;
+    const S* gb = reinterpret_cast<const S*>(L.gbuf) + (size_t)blockIdx.y * 3 * nbs;
+    S Fx = S(0), Fy = S(0), Fz = S(0);
+    const int Mi = d.nnb[atom], lb = d.lbo[atom];
+    for (int m = 0; m < Mi; ++m) {
+        const int r = d.revc[(size_t)m * N + atom];
+        Fx += gb[lb + m] - gb[r];
+        Fy += gb[nbs + lb + m] - gb[nbs + r];
+        Fz += gb[2 * nbs + lb + m] - gb[2 * nbs + r];
+    }
+    const S* fr = fref_of<S>(d);
+    S* a = abuf + (size_t)blockIdx.y * 3 * Ns;
+    a[la] = Fx - fr[atom];
+    a[Ns + la] = Fy - fr[(size_t)N + atom];
+    a[2 * Ns + la] = Fz - fr[(size_t)2 * N + atom];
+}
+
+template <typename S, int M, bool Full>
+__device__ __forceinline__ void run_large_adjoint(const BArgs<S>& A, const LArgs& L, int la, int atom,
+                                                  bool active, int Ns, const S* __restrict__ abuf) {
+    const SetDev& d = A.set;
+    const int N = d.N;
+    constexpr int MM = M > 0 ? M : 1;
+    constexpr int NX = Form<Full>::nx;
+    Geo<S, M> g;
+    g.load(geom_of<S>(d), N, atom, active, nullptr, d.kcap);
+    int jl[MM];
+#pragma unroll
+    for (int m = 0; m < M; ++m) jl[m] = (active && m < d.kcap) ? d.jl[(size_t)m * N + atom] : 0;
+    const int c = L.c0 + blockIdx.y;
+    S rec[kNParam];
+    decode_record<S, Full>(A.x + (size_t)NX * c, rec);
+    const S* a = abuf + (size_t)blockIdx.y * 3 * Ns;
+    const S ax = active ? a[la] : S(0), ay = active ? a[Ns + la] : S(0), az = active ? a[2 * Ns + la] : S(0);
+    S phi[NX];
+    // lanes past the structure have zero geometry: phi = 0
+    adjoint_phi<S, M, Full>(
+        g, rec, A.x + (size_t)NX * c, ax, ay, az,
+        [&](int m) {
+            int jm = jl[m];
+            asm volatile("" : "+v"(jm));
+            return Vec4<S>{a[jm], a[Ns + jm], a[2 * Ns + jm], S(0)};
+        },
+        A.coef + ((size_t)c * d.S + L.s) * 8, phi);
+    const int lane = threadIdx.x & 63;
+    const int slot = d.st_slot[L.s] + (la >> 6);
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = k < NX ? (double)phi[k < NX ? k : 0] : 0.0;
+    int vidx;
+    double sum = group_reduce8(v, 64, &vidx);
+    if ((lane & 7) == 0 && vidx < (NX < 8 ? NX : 8))
+        A.partial[((size_t)c * d.nslots + slot) * A.nv + vidx] = sum;
+    if constexpr (Full) {
+        double u[8];
+        u[0] = (double)phi[8];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) u[k] = 0.0;
+        sum = group_reduce8(u, 64, &vidx);
+        if ((lane & 7) == 0 && vidx == 0) A.partial[((size_t)c * d.nslots + slot) * A.nv + 8] = sum;
+    }
+}
+
+template <typename S, int MC, bool Full>
+__global__ __launch_bounds__(256) void k_large_adjoint(BArgs<S> A, LArgs L, const S* __restrict__ abuf) {
+    const SetDev& d = A.set;
+    const int a0 = d.st_off[L.s], Ns = d.st_off[L.s + 1] - a0;
+    const int la = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = la < Ns;
+    const int atom = a0 + (active ? la : 0);
+    const int Mi = active ? d.nnb[atom] : -1;
+    const int Mw = wave_max_int(Mi);
+    if (Mw < 0) return;                         // wavefronts past the structure own no slot
+    auto run = [&](auto mv) { run_large_adjoint<S, decltype(mv)::value, Full>(A, L, la, atom, active, Ns, abuf); };
+    if constexpr (MC <= 4) {
+        dispatch_m<0, MC>(Mw, run);
+    } else {
+        // two variants only: the dual passes of a wide variant take minutes to
+        // compile, and rows past the wave's coordination are padding bonds
+        if (Mw <= 8) run(std::integral_constant<int, 8>{});
+        else run(std::integral_constant<int, MC>{});
+    }
+}
+
 // Launchers, one per kernel family (defined in the mt_k_*.hip units).
 hipError_t launch_fit32(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<float>& A,
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
@@ -774,5 +895,12 @@ hipError_t launch_large32(int mc, int mode, int full, dim3 g, dim3 b, hipStream_
                           const BArgs<float>& A, const LArgs& L);
 hipError_t launch_large64(int mc, int mode, int full, dim3 g, dim3 b, hipStream_t st,
                           const BArgs<double>& A, const LArgs& L);
+// Two-pass fitness gradient of one structure and candidate chunk: force
+// residuals into abuf from the bond gradients staged by launch_large* in
+// MODE_STAGE, then the dual passes.
+hipError_t launch_large_adj32(int mc, int full, dim3 g, dim3 b, hipStream_t st, const BArgs<float>& Afit,
+                              const BArgs<float>& Aadj, const LArgs& L, float* abuf);
+hipError_t launch_large_adj64(int mc, int full, dim3 g, dim3 b, hipStream_t st, const BArgs<double>& Afit,
+                              const BArgs<double>& Aadj, const LArgs& L, double* abuf);
 
 }  // namespace mt

@@ -58,15 +58,18 @@ struct Geo {
     // cos(theta) values are formed and rounded once; from float unit vectors
     // they carry up to ~2e-7 absolute error, which zeta passes on to the
     // energy through (cos - h)^2.
+    // rows: neighbour rows the arrays hold (a variant wider than the set's
+    // capacity reads the rows past it as padding bonds)
     __device__ __forceinline__ void load(const GeomArrays<S>& G, int N, int atom, bool active,
-                                         const GeomArrays<double>* G64 = nullptr) {
+                                         const GeomArrays<double>* G64 = nullptr, int rows = M) {
         if constexpr (sizeof(S) == 4) {
             if (G.pk0) {
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     const size_t o = (size_t)m * N + atom;
-                    const float4 a = active ? G.pk0[o] : make_float4(0.f, 0.f, 0.f, 3.f);
-                    const float4 b = active ? G.pk1[o] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    const bool ok = active && m < rows;
+                    const float4 a = ok ? G.pk0[o] : make_float4(0.f, 0.f, 0.f, 3.f);
+                    const float4 b = ok ? G.pk1[o] : make_float4(0.f, 0.f, 0.f, 0.f);
                     ux[m] = a.x; uy[m] = a.y; uz[m] = a.z; rhi[m] = a.w;
                     rlo[m] = b.x; rinv[m] = b.y; fc[m] = b.z; hfcp[m] = b.w;
                 }
@@ -76,7 +79,10 @@ struct Geo {
 #pragma unroll
                         for (int m = 0; m < M; ++m) {
                             const size_t o = (size_t)m * N + atom;
-                            vx[m] = G64->ux[o]; vy[m] = G64->uy[o]; vz[m] = G64->uz[o];
+                            const bool ok = m < rows;
+                            vx[m] = ok ? G64->ux[o] : 0.0;
+                            vy[m] = ok ? G64->uy[o] : 0.0;
+                            vz[m] = ok ? G64->uz[o] : 0.0;
                         }
                         int p = 0;
 #pragma unroll
@@ -94,14 +100,15 @@ struct Geo {
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const size_t o = (size_t)m * N + atom;
-            ux[m] = active ? G.ux[o] : S(0);
-            uy[m] = active ? G.uy[o] : S(0);
-            uz[m] = active ? G.uz[o] : S(0);
-            rhi[m] = active ? G.rhi[o] : S(3);
-            rlo[m] = (active && G.rlo) ? G.rlo[o] : S(0);
-            rinv[m] = active ? G.rinv[o] : S(0);
-            fc[m] = active ? G.fc[o] : S(0);
-            hfcp[m] = active ? G.hfcp[o] : S(0);
+            const bool ok = active && m < rows;
+            ux[m] = ok ? G.ux[o] : S(0);
+            uy[m] = ok ? G.uy[o] : S(0);
+            uz[m] = ok ? G.uz[o] : S(0);
+            rhi[m] = ok ? G.rhi[o] : S(3);
+            rlo[m] = (ok && G.rlo) ? G.rlo[o] : S(0);
+            rinv[m] = ok ? G.rinv[o] : S(0);
+            fc[m] = ok ? G.fc[o] : S(0);
+            hfcp[m] = ok ? G.hfcp[o] : S(0);
         }
         cache_cos();
     }

@@ -34,19 +34,8 @@ __device__ __forceinline__ bool cand_valid(const double* x, int c, int full) {
     return full ? params_valid<true>(x + 9 * (size_t)c) : params_valid<false>(x + 6 * (size_t)c);
 }
 
-__device__ __forceinline__ void block_sum3(double* a, double (*sh)[256]) {
-    for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] = a[k];
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o)
-            for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + o];
-        __syncthreads();
-    }
-    for (int k = 0; k < 3; ++k) a[k] = sh[k][0];
-}
-
-// The same sums by an xor butterfly inside each wavefront, then the
-// wavefront totals added in wavefront order (fixed, so deterministic).
+// Block sums of three values: an xor butterfly inside each wavefront, then
+// the wavefront totals added in wavefront order (fixed, so deterministic).
 __device__ __forceinline__ void block_sum3_waves(double* a, double (*sh)[256]) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
@@ -98,31 +87,52 @@ __device__ __forceinline__ void struct_sums(const FinArgs& F, int c, int s, doub
 constexpr int kCoopSlots = 32;
 
 // Block-wide slot sums of structure s (all threads call; the result is valid
-// in every thread).  Each thread adds a fixed strided subset of the slots,
-// then a fixed tree adds the threads: the order depends only on the sizes.
+// in every thread).  Each thread adds a fixed strided subset of the slots
+// (loads unrolled over the 8 or 11 values), an xor butterfly adds the lanes of
+// each wavefront, and the wavefront totals are added in wavefront order: the
+// order depends only on the sizes.
+template <int NV>
+__device__ void coop_sums_n(const FinArgs& F, int c, int s, double* a, double (*sh)[256]) {
+    const SetDev& d = F.set;
+#pragma unroll
+    for (int k = 0; k < 11; ++k) a[k] = 0;
+    const int s0 = d.st_slot[s], s1 = d.st_slot[s + 1];
+    for (int sl = s0 + threadIdx.x; sl < s1; sl += blockDim.x) {
+        const double* p = F.partial + ((size_t)c * d.nslots + sl) * F.nv;
+        double v[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = p[k];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) a[k] += v[k];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) a[k] += __shfl_xor(a[k], o, 64);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();                       // sh may still be read by an earlier call
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[k][w] = a[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double t = sh[k][0];
+        for (int q = 1; q < nw; ++q) t += sh[k][q];
+        a[k] = t;
+    }
+    __syncthreads();
+}
+
 __device__ void coop_struct_sums(const FinArgs& F, int c, int s, double* e, double* w6, double* rf,
                                  double* j3, double (*sh)[256]) {
-    const SetDev& d = F.set;
     double a[11];
-    for (int k = 0; k < 11; ++k) a[k] = 0;
-    const int nv = F.nv >= 11 ? 11 : 8;
-    for (int sl = d.st_slot[s] + threadIdx.x; sl < d.st_slot[s + 1]; sl += blockDim.x) {
-        const double* p = F.partial + ((size_t)c * d.nslots + sl) * F.nv;
-        for (int k = 0; k < nv; ++k) a[k] += p[k];
-    }
-    __syncthreads();
-    for (int k = 0; k < 11; ++k) sh[k][threadIdx.x] = a[k];
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o)
-            for (int k = 0; k < 11; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + o];
-        __syncthreads();
-    }
-    *e = sh[0][0];
-    for (int k = 0; k < 6; ++k) w6[k] = sh[1 + k][0];
-    *rf = sh[7][0];
-    for (int k = 0; k < 3; ++k) j3[k] = sh[8 + k][0];
-    __syncthreads();
+    if (F.nv >= 11) coop_sums_n<11>(F, c, s, a, sh);
+    else coop_sums_n<8>(F, c, s, a, sh);
+    *e = a[0];
+    for (int k = 0; k < 6; ++k) w6[k] = a[1 + k];
+    *rf = a[7];
+    for (int k = 0; k < 3; ++k) j3[k] = a[8 + k];
 }
 
 __device__ __forceinline__ bool coop_struct(const SetDev& d, int s) {
@@ -162,7 +172,7 @@ __global__ __launch_bounds__(256) void k_finalize_fit(FinArgs F) {
         }
         acc[2] += rf;
     }
-    block_sum3(acc, sh);
+    block_sum3_waves(acc, sh);
     if (threadIdx.x == 0) {
         const bool ok = cand_valid(F.x, c, F.full);
         const double Ze = sqrt(acc[0] / F.Qe), Zv = sqrt(acc[1] / F.Qv), Zf = sqrt(acc[2] / F.Qf);
@@ -362,7 +372,7 @@ __global__ __launch_bounds__(256) void k_finalize_eval(FinArgs F) {
             for (int k = 0; k < 6; ++k) F.virial[((size_t)c * d.S + s) * 6 + k] = ok ? w6[k] : nan;
         for (int k = 0; k < 3; ++k) jacc[k] += j3[k];
     }
-    block_sum3(jacc, sh);
+    block_sum3_waves(jacc, sh);
     if (threadIdx.x == 0 && F.heat)
         for (int k = 0; k < 3; ++k) F.heat[3 * c + k] = ok ? jacc[k] : nan;
 }

@@ -143,6 +143,50 @@ def test_fitness_gradient_two_pass(api, precision):
     ts.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_one_large_structure_set(api, precision):
+    """A set of one 600-atom packing (the molecular-dynamics shape: two-pass
+    path, all slots summed by the whole block): E, W and the heat current J of
+    three candidates, one invalid (NaN and isolated), against the oracle and
+    against the same structure beside a 64-atom cell; a repeated call gives the
+    same bits."""
+    g = rng(34)
+    big = W.random_packing(g, 600)
+    s1 = W.make_set([big])
+    s2 = W.make_set([big] + W.strained_diamond_cells(35, 1))
+    X = W.draw_params(rng(80), 3)
+    X[1, 0] = -1.0                                          # D0 <= 0
+    vel = rng(81).normal(0.0, 0.01, size=(600, 3))
+    ts1, ts2 = api.from_structures(s1), api.from_structures(s2)
+    assert ts1.stats()["n_large"] == 1 and ts1.stats()["n_struct"] == 1
+    o1 = {k: v.cpu().numpy() for k, v in ts1.tersoff_eval(X, precision=precision, velocities=vel).items()}
+    o1b = {k: v.cpu().numpy() for k, v in ts1.tersoff_eval(X, precision=precision, velocities=vel).items()}
+    for k in o1:
+        assert np.array_equal(o1[k], o1b[k], equal_nan=True), k
+    vel2 = np.vstack([vel, np.zeros((64, 3))])
+    o2 = {k: v.cpu().numpy() for k, v in ts2.tersoff_eval(X, precision=precision, velocities=vel2).items()}
+    assert np.isnan(o1["E"][1]).all() and np.isnan(o1["W"][1]).all() and np.isnan(o1["J"][1]).all()
+    for c in (0, 2):
+        ref = T.evaluate_set(s1, X[c], R1, R2, velocities=vel)
+        if precision == "fp64":
+            assert abs(o1["E"][c, 0] - ref["E"][0]) <= 1e-10 * abs(ref["E"][0])
+            assert np.abs(o1["W"][c, 0] - ref["W6"][0]).max() <= 1e-10 * np.abs(ref["W6"][0]).max()
+            assert np.abs(o1["J"][c] - ref["J"]).max() <= 1e-10 * np.abs(ref["J"]).max()
+            rel = 1e-12
+        else:
+            assert abs(o1["E"][c, 0] - ref["E"][0]) / 600 <= 1e-6
+            assert np.abs(o1["W"][c, 0] - ref["W6"][0]).max() / 600 <= 1e-5
+            assert np.abs(o1["J"][c] - ref["J"]).max() <= 1e-5 * np.abs(ref["J"]).max()
+            rel = 1e-12
+        # the same slots summed beside another structure
+        assert abs(o1["E"][c, 0] - o2["E"][c, 0]) <= rel * abs(o2["E"][c, 0])
+        assert np.abs(o1["W"][c, 0] - o2["W"][c, 0]).max() <= rel * np.abs(o2["W"][c, 0]).max()
+        assert np.abs(o1["J"][c] - o2["J"][c]).max() <= rel * np.abs(o2["J"][c]).max()
+        assert np.abs(o1["F"][c] - o2["F"][c, :600]).max() <= 1e-12 * np.abs(o2["F"][c, :600]).max()
+    ts1.close()
+    ts2.close()
+
+
 def test_graph_replay_after_the_staging_buffer_grows(api):
     """A captured fitness graph holds the address of the two-pass staging
     buffer (structures over 512 atoms).  A float64 call and a larger population

@@ -58,9 +58,9 @@ PMC_TRAFFIC = {
     "sources": ["paper_1909_11474_amd/csrc/mt_common.h", "paper_1909_11474_amd/csrc/mt_site.h",
                 "paper_1909_11474_amd/csrc/mt_kernels.h", "paper_1909_11474_amd/csrc/mt_k_fit32.hip",
                 "paper_1909_11474_amd/csrc/mt_eval.hip"],
-    "sha256_16": "48b07cc5f5b1c04a",
-    "fetch_bytes": 42007.0 * 1024 * 2.00,
-    "write_bytes": 62407.1 * 1024 * 1.00,
+    "sha256_16": "5a837a64f9bf34b8",
+    "fetch_bytes": 44956.2 * 1024 * 2.00,
+    "write_bytes": 48789.3 * 1024 * 1.00,
 }
 
 

@@ -402,8 +402,15 @@ static int grad_impl(mt_set* set, const double* x, int form, int P, const double
     if (!dZdx) return fail(MT_EINVAL, "dZdx must not be NULL");
     hipStream_t st = (hipStream_t)stream;
     TRY(ensure_workspace(set, P, kNVFit));
+    // force residuals of the batched atoms, written by the fitness and read by
+    // the adjoint
+    HIPCHECK(set->resid.reserve((precision == MT_FP64 ? sizeof(double) : sizeof(float)) * 3 * (size_t)P *
+                                set->N));
     set->fit_P = 0;
-    TRY(fitness_sequence(set, x, form, P, w, precision, MT_BATCHED, Z, st));
+    set->grad_resid = set->resid.p;
+    const int frc = fitness_sequence(set, x, form, P, w, precision, MT_BATCHED, Z, st);
+    set->grad_resid = nullptr;
+    TRY(frc);
     set->fit_P = P;
     set->fit_form = form;
     const LaunchCfg cfg = cfg_for(set, P, precision);

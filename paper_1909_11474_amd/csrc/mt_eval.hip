@@ -759,6 +759,10 @@ int launch_batched(mt_set* set, const LaunchCfg& cfg, int P, int precision, int 
     Af.vel = Ad.vel = vel;
     Af.force = Ad.force = force;
     Af.atom_virial = Ad.atom_virial = atom_virial;
+    if (mode == MODE_FIT && set->grad_resid) {
+        Af.resid = static_cast<float*>(set->grad_resid);
+        Ad.resid = static_cast<double*>(set->grad_resid);
+    }
     TRY_RC(run_plan(set, plan, cfg, fam, Af, Ad, 0, st));
     if (plan->twopass.empty()) return MT_OK;
     TRY_RC(reserve_twopass(set, plan, P, precision));     // no-op once reserved
@@ -1059,6 +1063,11 @@ static int adjoint_common(mt_set* set, const LaunchCfg& cfg, int P, int precisio
     BArgs<float> Af = make_args<float>(set, set->partial2.as<double>(), nv);
     BArgs<double> Ad = make_args<double>(set, set->partial2.as<double>(), nv);
     Af.coef = Ad.coef = set->zwork.as<double>();
+    // the fitness call before this one wrote the batched atoms' residuals (a
+    // structure the adjoint batches needs no more LDS in the fitness, so the
+    // fitness batched it too)
+    Af.resid = set->resid.as<float>();
+    Ad.resid = set->resid.as<double>();
     TRY_RC(run_plan(set, plan, cfg, fam, Af, Ad, 1, st));
     // structures over the batched limit, and those whose adjoint does not fit
     // one block's LDS, take the two-pass adjoint
@@ -1075,12 +1084,6 @@ static int adjoint_common(mt_set* set, const LaunchCfg& cfg, int P, int precisio
 int launch_adjoint(mt_set* set, const LaunchCfg& cfg, int P, int precision, const double* w,
                    const double* Z, hipStream_t st) {
     return adjoint_common(set, cfg, P, precision, w, Z, st);
-}
-
-int launch_adjoint_plain(mt_set* set, int P, int precision, const double* w, const double* Z,
-                         hipStream_t st) {
-    LaunchCfg plain;
-    return adjoint_common(set, plain, P, precision, w, Z, st);
 }
 
 int launch_finalize_grad(mt_set* set, int P, const double* Z, double* dZdx, hipStream_t st) {

@@ -139,6 +139,11 @@ struct mt_set {
     mt::DevBuf partial;                      // [P][nslots][NV] double
     mt::DevBuf partial2;                     // gradient partials
     mt::DevBuf abuf;                         // two-pass adjoint: staged force residuals
+    // fitness_grad: the fitness writes each batched atom's force residual
+    // F - F* here ([P][3][N] in the call's arithmetic, sorted atom order) and
+    // the adjoint reads it; grad_resid is set only for that fitness call
+    mt::DevBuf resid;
+    void* grad_resid = nullptr;
     mt::DevBuf zwork;                        // [P][4] scratch for fitness_grad
     mt::DevBuf gbuf;                         // large path bond gradients
     mt::DevBuf scalars;                      // small device scratch
@@ -199,10 +204,10 @@ int launch_finalize_eval(mt_set* set, int P, double* energy, double* virial, dou
 // sums in the set's workspace (set->cur_x and cur_form select the candidates'
 // domain check).
 int launch_fitness_terms(mt_set* set, int P, double* e, double* w, double* rf, hipStream_t stream);
+// The adjoint of the batched structures reads the force residuals the
+// fitness call just before it wrote to set->resid (set->grad_resid).
 int launch_adjoint(mt_set* set, const LaunchCfg& cfg, int P, int precision, const double* w,
                    const double* Z, hipStream_t stream);
-int launch_adjoint_plain(mt_set* set, int P, int precision, const double* w, const double* Z,
-                         hipStream_t stream);
 int launch_finalize_grad(mt_set* set, int P, const double* Z, double* dZdx, hipStream_t stream);
 
 // MODE_STAGE (two-pass path only): stage the bond gradients, no partial sums

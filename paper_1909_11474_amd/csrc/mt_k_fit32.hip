@@ -7,6 +7,7 @@ namespace mt {
 
 hipError_t launch_fit32(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<float>& A,
                       hipEvent_t e0, hipEvent_t e1) {
+    if (A.resid) return launch_fitr32(mc, 0, g, b, lds, st, A, e0, e1);
     switch (mc) {
         case 4: hipExtLaunchKernelGGL((k_batched<float, MODE_FIT, 4>), g, b, lds, st, e0, e1, 0, A); break;
         case 6: hipExtLaunchKernelGGL((k_batched<float, MODE_FIT, 6>), g, b, lds, st, e0, e1, 0, A); break;

@@ -8,6 +8,7 @@ namespace mt {
 
 hipError_t launch_fit32f(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<float>& A,
                         hipEvent_t e0, hipEvent_t e1) {
+    if (A.resid) return launch_fitr32(mc, 1, g, b, lds, st, A, e0, e1);
     switch (mc) {
         case 4: hipExtLaunchKernelGGL((k_batched<float, MODE_FIT, 4, true>), g, b, lds, st, e0, e1, 0, A); break;
         case 16: hipExtLaunchKernelGGL((k_batched<float, MODE_FIT, 16, true>), g, b, lds, st, e0, e1, 0, A); break;

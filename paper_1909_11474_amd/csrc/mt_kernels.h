@@ -145,6 +145,9 @@ struct BArgs {
     const double* vel;        // [3][N]
     // adjoint inputs
     const double* coef;       // [P][S][8]
+    // force residuals F - F* of the batched atoms, [P][3][N] (sorted atom
+    // order): written by the fitness kernel when non-null, read by the adjoint
+    S* resid;
 };
 
 template <typename S>
@@ -236,7 +239,10 @@ __device__ __forceinline__ size_t lds_param_bytes(int nc) {
     return ((size_t)nc * kNParam * sizeof(S) + 31) & ~(size_t)31;
 }
 
-template <typename S, int MODE, int M, int GF = 0, bool Full = false>
+// Resid (fitness mode): also write each atom's force residual to A.resid (the
+// gradient's fitness call; a separate instance, so the fitness alone carries
+// no trace of it).
+template <typename S, int MODE, int M, int GF = 0, bool Full = false, bool Resid = false>
 __device__ __forceinline__ void run_batched(const BArgs<S>& A, const Item& it, const ItemCtx& x,
                                             unsigned char* __restrict__ lds) {
     const SetDev& d = A.set;
@@ -315,6 +321,12 @@ __device__ __forceinline__ void run_batched(const BArgs<S>& A, const Item& it, c
         if (MODE == MODE_FIT) {
             const S ax = Fx - frx, ay = Fy - fry, az = Fz - frz;
             v[7] = (double)(ax * ax + ay * ay + az * az);
+            if (Resid && cok) {
+                S* r = A.resid + (size_t)c * 3 * N;
+                r[x.atom] = ax;
+                r[(size_t)N + x.atom] = ay;
+                r[(size_t)2 * N + x.atom] = az;
+            }
             store_group<GF>(v, x, group_ok, A.partial, d.nslots, A.nv, c, 0, 0xff);
         } else {
             v[7] = 0.0;
@@ -375,7 +387,7 @@ __device__ __forceinline__ void decode_item(const BArgs<S>& A, const Item& it, u
     __syncthreads();
 }
 
-template <typename S, int MODE, int MC, bool Full>
+template <typename S, int MODE, int MC, bool Full, bool Resid = false>
 __device__ __forceinline__ void batched_item(const BArgs<S>& A, const Item& it, unsigned char* lds) {
     decode_item<S, Full>(A, it, lds);
     const ItemCtx x = item_ctx(A.set, it);
@@ -394,11 +406,11 @@ __device__ __forceinline__ void batched_item(const BArgs<S>& A, const Item& it, 
         // in-place lane swaps
         if constexpr (MODE == MODE_FIT && sizeof(S) == 4 && !Full) {
             if (x.g == 64) {
-                run_batched<S, MODE, decltype(mv)::value, 64, Full>(A, it, x, lds);
+                run_batched<S, MODE, decltype(mv)::value, 64, Full, Resid>(A, it, x, lds);
                 return;
             }
         }
-        run_batched<S, MODE, decltype(mv)::value, 0, Full>(A, it, x, lds);
+        run_batched<S, MODE, decltype(mv)::value, 0, Full, Resid>(A, it, x, lds);
     });
 }
 
@@ -409,14 +421,14 @@ struct WavesPerEU {
     static constexpr int value = (MC <= 4 && sizeof(S) == 4 && MODE == MODE_FIT) ? 4 : 1;
 };
 
-template <typename S, int MODE, int MC, bool Full = false>
+template <typename S, int MODE, int MC, bool Full = false, bool Resid = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S, MODE, MC>::value)))
 void k_batched(BArgs<S> A) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int b0 = A.bin_off[blockIdx.x], b1 = A.bin_off[blockIdx.x + 1];
     for (int i = b0; i < b1; ++i) {
         const Item it = A.items[i];
-        batched_item<S, MODE, MC, Full>(A, it, lds_raw);
+        batched_item<S, MODE, MC, Full, Resid>(A, it, lds_raw);
         __syncthreads();
     }
 }
@@ -519,15 +531,9 @@ __device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, c
     g.load(geom_of<S>(d), N, x.atom, x.active);
     constexpr int MM = M > 0 ? M : 1;
     constexpr int NX = Form<Full>::nx;
-    int rv[MM], jl[MM];
+    int jl[MM];
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        rv[m] = x.active ? d.rev[(size_t)m * N + x.atom] + x.q * x.xsz : x.own + m * x.g;
-        jl[m] = x.active ? d.jl[(size_t)m * N + x.atom] : x.la;
-    }
-    const S* fr = fref_of<S>(d);
-    S frx = S(0), fry = S(0), frz = S(0);
-    if (x.active) { frx = fr[x.atom]; fry = fr[(size_t)N + x.atom]; frz = fr[(size_t)2 * N + x.atom]; }
+    for (int m = 0; m < M; ++m) jl[m] = x.active ? d.jl[(size_t)m * N + x.atom] : x.la;
 
     for (int step = 0; step < x.steps; ++step) {
         const int cl = x.q + step * x.R;
@@ -535,26 +541,13 @@ __device__ __forceinline__ void run_adjoint(const BArgs<S>& A, const Item& it, c
         const int clv = group_ok ? cl : 0;
         const int c = it.c0 + clv;
         const S* prec = pbuf + kNParam * clv;
-        // plain pass: force residual of this atom
+        // this atom's force residual, from the fitness call (lanes outside the
+        // structure: zero, and zero geometry)
         S ax = S(0), ay = S(0), az = S(0);
-        {
-            Cand<S, S, Full> pp;
-            load_cand(prec, pp);
-            double U0;
-            S Gx[MM], Gy[MM], Gz[MM];
-            site_eval<S, S, M>(g, pp, U0, Gx, Gy, Gz);
-#pragma unroll
-            for (int m = 0; m < M; ++m) xb[x.own + m * x.g] = Vec4<S>{Gx[m], Gy[m], Gz[m], S(0)};
-            exchange_sync(x.block_sync);
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                const Vec4<S> r = xb[rv[m]];
-                ax += Gx[m] - r.x;
-                ay += Gy[m] - r.y;
-                az += Gz[m] - r.z;
-            }
+        if (x.active) {
+            const S* r = A.resid + (size_t)c * 3 * N;
+            ax = r[x.atom]; ay = r[(size_t)N + x.atom]; az = r[(size_t)2 * N + x.atom];
         }
-        ax -= frx; ay -= fry; az -= frz;
         ab[x.la] = Vec4<S>{ax, ay, az, S(0)};
         exchange_sync(x.block_sync);
         S phi[NX];
@@ -589,7 +582,7 @@ __device__ __forceinline__ void adjoint_item(const BArgs<S>& A, const Item& it, 
     const int Mi = x.active ? A.set.nnb[x.atom] : -1;
     const int Mw = wave_max_int(Mi);
     if (Mw < 0) {
-        run_idle(x.steps, 3);
+        run_idle(x.steps, 2);
         return;
     }
     dispatch_m<ClassLo<MC>::value, MC>(Mw, [&](auto mv) {
@@ -874,6 +867,15 @@ hipError_t launch_adj32f(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, con
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_adj64f(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<double>& A,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// The fitness kernels that also write the force residuals (A.resid), for the
+// gradient's fitness call; the launch_fit* launchers pick them when A.resid
+// is set.
+hipError_t launch_fitr32(int mc, int full, dim3 g, dim3 b, size_t lds, hipStream_t st,
+                         const BArgs<float>& A, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_fitr64(int mc, int full, dim3 g, dim3 b, size_t lds, hipStream_t st,
+                         const BArgs<double>& A, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_fitr32f(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<float>& A,
+                          hipEvent_t e0, hipEvent_t e1);
 // Tersoff-form (nine-parameter) batched families.
 hipError_t launch_fit32f(int mc, dim3 g, dim3 b, size_t lds, hipStream_t st, const BArgs<float>& A,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);

@@ -24,7 +24,8 @@ schedule (one launch per candidate and structure), the GA batch (200
 candidates x 100 strained 64-atom cells), the fitness gradient (64 candidates
 over the uneven set), the GA with top-8 gradient refinement against the plain
 GA for 500 generations, the nine-parameter Tersoff form, the 64,000-atom force
-call, the 0 K property layer and HNEMD, and times the CPU oracle on a bounded
+call, the 0 K property layer and HNEMD, and times the CPU oracle (the plain C
+reference, and the autograd one beside it) on a bounded
 sample.  Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -58,9 +59,9 @@ PMC_TRAFFIC = {
     "sources": ["paper_1909_11474_amd/csrc/mt_common.h", "paper_1909_11474_amd/csrc/mt_site.h",
                 "paper_1909_11474_amd/csrc/mt_kernels.h", "paper_1909_11474_amd/csrc/mt_k_fit32.hip",
                 "paper_1909_11474_amd/csrc/mt_eval.hip"],
-    "sha256_16": "5a837a64f9bf34b8",
-    "fetch_bytes": 44956.2 * 1024 * 2.00,
-    "write_bytes": 48789.3 * 1024 * 1.00,
+    "sha256_16": "13f257fa46dbe3be",
+    "fetch_bytes": 43560.4 * 1024 * 2.00,
+    "write_bytes": 34659.8 * 1024 * 1.00,
 }
 
 
@@ -363,18 +364,52 @@ def oracle_rate(args, torch, wl, refs, grad: bool, seconds=None):
     return out
 
 
+def c_oracle_rate(wl, refs, top, seconds, threads=0):
+    """The plain C float64 reference's fitness rate (chain-rule forces, OpenMP
+    over candidates) on the workload's structures: the population in chunks of
+    64 candidates, wrapping round, until `seconds` are spent."""
+    from oracle import c_oracle as C
+    s = wl.structs
+    r = {"e": refs[0].cpu().numpy(), "w": refs[1].cpu().numpy(), "f": refs[2].cpu().numpy()}
+    ctop = C.CTopology(s, wl.R2, entries=(top.i, top.j, top.shift, top.sob))
+    nt = threads or C.max_threads()
+    X = wl.population
+    P = X.shape[0]
+    C.fitness(s, X[:1], r, topology=ctop, threads=nt)                 # warm-up
+    done, k = 0, 0
+    c0 = time.perf_counter()
+    while done == 0 or time.perf_counter() - c0 < seconds:
+        chunk = X[k:k + 64] if k + 64 <= P else np.concatenate([X[k:], X[:k + 64 - P]])
+        C.fitness(s, chunk, r, topology=ctop, threads=nt)
+        done += chunk.shape[0]
+        k = (k + 64) % P
+    tc = time.perf_counter() - c0
+    return {"value": done * s.n_atoms / tc, "unit": "atom·candidate evals/s", "cores": int(nt),
+            "kind": "oracle",
+            "sample": f"{done} candidate evaluations of the fitness x all {s.n_struct} structures "
+                      f"({s.n_atoms} atoms) in {tc:.1f} s, plain C float64 (oracle/tersoff_c.c: "
+                      f"forces by the chain rule, OpenMP over candidates)"}
+
+
 def cpu_baseline_headline(args, torch, wl, refs):
-    """The oracle on the headline workload: all host threads for the CPU budget,
-    then one thread for a third of it."""
-    out = oracle_rate(args, torch, wl, refs, grad=False, seconds=args.cpu_seconds)
+    """The oracle on the headline workload: the plain C reference on all host
+    threads for the CPU budget and on one thread for a third of it, beside the
+    autograd oracle (all threads, a third of the budget)."""
+    from oracle import tersoff as T
+    key = (wl.seeds["structures"], wl.structs.n_struct, wl.structs.n_atoms, wl.R2)
+    t0 = time.perf_counter()
+    if key not in _ORACLE_TOPOLOGY:
+        _ORACLE_TOPOLOGY[key] = T.topology(wl.structs, wl.R2)
+    t_top = time.perf_counter() - t0
+    top = _ORACLE_TOPOLOGY[key]
+    out = c_oracle_rate(wl, refs, top, args.cpu_seconds)
+    out["setup_s"] = {"topology": t_top}
     out["host"] = {"nproc": os.cpu_count(), "cpu_model": cpu_model()}
-    threads = torch.get_num_threads()
-    torch.set_num_threads(1)
-    try:
-        one = oracle_rate(args, torch, wl, refs, grad=False, seconds=args.cpu_seconds / 3)
-    finally:
-        torch.set_num_threads(threads)
+    one = c_oracle_rate(wl, refs, top, args.cpu_seconds / 3, threads=1)
     out["one_thread"] = {"value": one["value"], "cores": 1, "sample": one["sample"]}
+    out["autograd_oracle"] = oracle_rate(args, torch, wl, refs, grad=False, seconds=args.cpu_seconds / 3)
+    log(f"cpu oracle (plain C, {out['cores']} threads): {out['value']:.4e} atom*cand/s; "
+        f"one thread {one['value']:.4e}")
     return out
 
 
@@ -464,7 +499,12 @@ def ga_batch(args, api, torch, W, dev):
                                "ms_per_step": tg.seconds / args.grad_steps * 1e3}
     ts.close()
     if not args.no_cpu_baseline:
-        out["cpu_oracle"] = oracle_rate(args, torch, wl, refs, grad=False)
+        from oracle import tersoff as T
+        key = (wl.seeds["structures"], wl.structs.n_struct, wl.structs.n_atoms, wl.R2)
+        if key not in _ORACLE_TOPOLOGY:
+            _ORACLE_TOPOLOGY[key] = T.topology(wl.structs, wl.R2)
+        out["cpu_oracle"] = c_oracle_rate(wl, refs, _ORACLE_TOPOLOGY[key], args.cpu_seconds / 3)
+        out["cpu_oracle"]["autograd_oracle"] = oracle_rate(args, torch, wl, refs, grad=False)
     return out
 
 

@@ -14,7 +14,11 @@ What it computes, each item written out from the paper's definitions:
 * forces, virial and per-atom virial: derivatives of that energy, taken by
   PyTorch autograd in float64 (forces = -dE/dr, virial = -dE/d(strain));
 * the fitness Z = w_e Z_e + w_v Z_v + w_f Z_f of Sec. III.B and its gradient
-  with respect to the six parameters, also by autograd.
+  with respect to the six parameters, also by autograd;
+* a plain C float64 build of the energy, forces, virials and fitness
+  (``tersoff_c.c`` through ``c_oracle.py``), with the derivatives written out
+  by the chain rule and candidates spread over OpenMP threads: the benchmark's
+  CPU baseline, held to the autograd version by the CPU tests.
 
 Parity status: every function here is pinned by the CPU tests against values
 the paper prints (cohesive energy, lattice constant, elastic constants) and

@@ -87,38 +87,43 @@ __device__ __forceinline__ void struct_sums(const FinArgs& F, int c, int s, doub
 constexpr int kCoopSlots = 32;
 
 // Block-wide slot sums of structure s (all threads call; the result is valid
-// in every thread).  Each thread adds a fixed strided subset of the slots
-// (loads unrolled over the 8 or 11 values), an xor butterfly adds the lanes of
-// each wavefront, and the wavefront totals are added in wavefront order: the
-// order depends only on the sizes.
+// in every thread).  The structure's [slots][nv] partial sums are read as one
+// flat array, consecutive threads on consecutive values (coalesced: a strided
+// read of whole slots per thread makes every load instruction touch 64 cache
+// lines).  With nv (8 or 16) dividing the block, thread t only ever sees value
+// t % nv; an xor butterfly over the lanes of equal value index and the
+// wavefront totals in wavefront order finish the sums, so the order depends
+// only on the sizes.
 template <int NV>
 __device__ void coop_sums_n(const FinArgs& F, int c, int s, double* a, double (*sh)[256]) {
     const SetDev& d = F.set;
-#pragma unroll
-    for (int k = 0; k < 11; ++k) a[k] = 0;
     const int s0 = d.st_slot[s], s1 = d.st_slot[s + 1];
-    for (int sl = s0 + threadIdx.x; sl < s1; sl += blockDim.x) {
-        const double* p = F.partial + ((size_t)c * d.nslots + sl) * F.nv;
-        double v[NV];
+    const int nv = F.nv;                           // 8 or 16, a power of two
+    const double* base = F.partial + ((size_t)c * d.nslots + s0) * nv;
+    const int total = (s1 - s0) * nv;
+    const int bd = blockDim.x;
+    double acc = 0.0;
+    // sixteen loads in flight per thread before their adds (the last batch
+    // predicated: a serial tail would wait for each load in turn)
+    for (int e = threadIdx.x; e < total; e += 16 * bd) {
+        double v[16];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] = p[k];
+        for (int u = 0; u < 16; ++u) v[u] = e + u * bd < total ? base[e + u * bd] : 0.0;
 #pragma unroll
-        for (int k = 0; k < NV; ++k) a[k] += v[k];
+        for (int u = 0; u < 16; ++u) acc += v[u];
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) a[k] += __shfl_xor(a[k], o, 64);
-    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int o = nv; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = bd >> 6;
     __syncthreads();                       // sh may still be read by an earlier call
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) sh[k][w] = a[k];
+    if (lane < nv && lane < 11) sh[lane][w] = acc;   // values 11.. of a slot are unused
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        double t = sh[k][0];
-        for (int q = 1; q < nw; ++q) t += sh[k][q];
+    for (int k = 0; k < 11; ++k) {
+        double t = 0.0;
+        if (k < NV) {
+            t = sh[k][0];
+            for (int q = 1; q < nw; ++q) t += sh[k][q];
+        }
         a[k] = t;
     }
     __syncthreads();

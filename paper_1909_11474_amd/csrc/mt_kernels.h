@@ -630,7 +630,9 @@ __device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L
     load_cand(rec, p);
     double U;
     S Gx[MM], Gy[MM], Gz[MM];
-    site_eval<S, S, M, E64>(g, p, U, Gx, Gy, Gz);
+    // about one wavefront per SIMD for a large structure: the bonds' float64
+    // energy chains interleave
+    site_eval<S, S, M, E64, Full, false>(g, p, U, Gx, Gy, Gz);
     S* gb = reinterpret_cast<S*>(L.gbuf) + (size_t)blockIdx.y * 3 * nbs;
     if (active) {
 #pragma unroll
@@ -700,9 +702,16 @@ __global__ __launch_bounds__(256) void k_large_gather(BArgs<S> A, LArgs L) {
     for (int k = 0; k < 9; ++k) wi[k] = S(0);
     if (active) {
         const int Mi = d.nnb[atom], lb = d.lbo[atom];
-        for (int m = 0; m < Mi; ++m) {
+        // every bond's reverse index first, then every staged gradient: two
+        // dependent memory round trips per atom instead of two per bond
+        int rv[MT_MAX_NBR];
+#pragma unroll
+        for (int m = 0; m < MT_MAX_NBR; ++m) rv[m] = m < Mi ? d.revc[(size_t)m * N + atom] : 0;
+#pragma unroll
+        for (int m = 0; m < MT_MAX_NBR; ++m) {
+            if (m >= Mi) break;
             const size_t o = (size_t)m * N + atom;
-            const int r = d.revc[o];
+            const int r = rv[m];
             const S rx = gb[r], ry = gb[nbs + r], rz = gb[2 * nbs + r];
             Fx += gb[lb + m] - rx;
             Fy += gb[nbs + lb + m] - ry;

@@ -301,8 +301,12 @@ constexpr int kPairwiseMax = 8;
 // dual passes over the same site would otherwise hold every shared primal
 // value across passes).  The barriers act on the caller's geometry in place
 // (they change no value), so no second copy of it becomes live.
+// SerialE64: keep the float64 energy chains of the bonds one after another
+// (fewer live registers; a kernel with other wavefronts to switch to loses
+// nothing), or let them interleave (a kernel that runs about one wavefront per
+// SIMD needs the instruction-level parallelism).
 template <typename V, typename S, int M, bool Energy64, bool PerBond, bool Fresh = false,
-          bool Full = false, typename Sink>
+          bool Full = false, bool SerialE64 = true, typename Sink>
 __device__ __forceinline__ void site_eval_sink(Geo<S, M>& g, const Cand<V, S, Full>& p,
                                                typename EnergyOf<V>::type& U, Sink&& sink) {
     constexpr int MM = M > 0 ? M : 1;
@@ -407,7 +411,7 @@ __device__ __forceinline__ void site_eval_sink(Geo<S, M>& g, const Cand<V, S, Fu
         cc[j] = (p.ccs * g.fc[j]) * (bfA * zn) * drcp(zsafe * onep);
         // per-bond sweep: keep the scheduler from interleaving all M bonds' chains
         // (about ten live values each; float64 ones in the energy mode)
-        if constexpr (PerBond || kE64) __builtin_amdgcn_sched_barrier(0);
+        if constexpr (PerBond || (kE64 && SerialE64)) __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (kE64) U = 0.5 * usum64; else U = S(0.5) * usum;
     if constexpr (PerBond) {
@@ -477,12 +481,12 @@ __device__ __forceinline__ void site_eval_sink(Geo<S, M>& g, const Cand<V, S, Fu
 }
 
 // The site routine with the bond gradients returned in arrays.
-template <typename V, typename S, int M, bool Energy64 = false, bool Full = false>
+template <typename V, typename S, int M, bool Energy64 = false, bool Full = false, bool SerialE64 = true>
 __device__ __forceinline__ void site_eval(Geo<S, M>& g, const Cand<V, S, Full>& p,
                                           typename EnergyOf<V>::type& U,
                                           V* __restrict__ Gx, V* __restrict__ Gy,
                                           V* __restrict__ Gz) {
-    site_eval_sink<V, S, M, Energy64, (M > kPairwiseMax)>(
+    site_eval_sink<V, S, M, Energy64, (M > kPairwiseMax), false, Full, SerialE64>(
         g, p, U, [&](int j, const V& x, const V& y, const V& z) {
             Gx[j] = x;
             Gy[j] = y;

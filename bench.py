@@ -59,9 +59,9 @@ PMC_TRAFFIC = {
     "sources": ["paper_1909_11474_amd/csrc/mt_common.h", "paper_1909_11474_amd/csrc/mt_site.h",
                 "paper_1909_11474_amd/csrc/mt_kernels.h", "paper_1909_11474_amd/csrc/mt_k_fit32.hip",
                 "paper_1909_11474_amd/csrc/mt_eval.hip"],
-    "sha256_16": "13f257fa46dbe3be",
-    "fetch_bytes": 43560.4 * 1024 * 2.00,
-    "write_bytes": 34659.8 * 1024 * 1.00,
+    "sha256_16": "a4bf6a420509e697",
+    "fetch_bytes": 43573.3 * 1024 * 2.00,
+    "write_bytes": 34689.2 * 1024 * 1.00,
 }
 
 

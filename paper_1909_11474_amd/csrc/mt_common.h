@@ -37,6 +37,9 @@ namespace mt {
 
 constexpr int kMaxNbr = 16;        // template limit on coordination
 constexpr int kMaxBatched = 512;   // largest structure of the batched kernel
+// Threads per block of the two-pass kernels; a structure over the batching
+// limit has one partial-sum slot per such block.
+constexpr int kLargeBlock = 256;
 constexpr int kNVFit = 8;          // partial sums per slot: E, W6, |F - F*|^2
 constexpr int kNVEval = 16;        // E, W6, |F-F*|^2, J3, unused
 constexpr int kNVGrad = 8;         // dZ/dx (6), unused (2)

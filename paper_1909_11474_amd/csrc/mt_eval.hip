@@ -82,9 +82,10 @@ __device__ __forceinline__ void struct_sums(const FinArgs& F, int c, int s, doub
     }
 }
 
-// Structures with more partial-sum slots than this (more than 2,048 atoms)
-// are summed by the whole block; smaller ones by one thread each.
-constexpr int kCoopSlots = 32;
+// Structures with more partial-sum slots than this (over 2,048 atoms: a
+// structure over the batching limit has one slot per 256-atom block, a batched
+// one at most 8) are summed by the whole block; smaller ones by one thread each.
+constexpr int kCoopSlots = 8;
 
 // Block-wide slot sums of structure s (all threads call; the result is valid
 // in every thread).  The structure's [slots][nv] partial sums are read as one
@@ -926,13 +927,13 @@ static int launch_twopass_t(mt_set* set, const std::vector<int>& structs, int P,
         }
         for (int c0 = 0; c0 < P; c0 += chunk) {
             const int nc = std::min(chunk, P - c0);
-            LArgs L{s, c0, set->gbuf.p};
-            dim3 grid(grid_of(ns, 256), nc);
+            LArgs L{s, c0, set->gbuf.p, set->h_large[s] ? 1 : 0};
+            dim3 grid(grid_of(ns, kLargeBlock), nc);
             hipError_t e;
             if constexpr (std::is_same<S, double>::value)
-                e = launch_large64(mc, mode, set->cur_form, grid, dim3(256), st, A, L);
+                e = launch_large64(mc, mode, set->cur_form, grid, dim3(kLargeBlock), st, A, L);
             else
-                e = launch_large32(mc, mode, set->cur_form, grid, dim3(256), st, A, L);
+                e = launch_large32(mc, mode, set->cur_form, grid, dim3(kLargeBlock), st, A, L);
             HIPCHECK(e);
         }
     }
@@ -1040,13 +1041,15 @@ static int launch_twopass_adjoint(mt_set* set, const std::vector<int>& structs, 
         }
         for (int c0 = 0; c0 < P; c0 += chunk) {
             const int nc = std::min(chunk, P - c0);
-            LArgs L{s, c0, set->gbuf.p};
-            dim3 grid(grid_of(ns, 256), nc);
+            LArgs L{s, c0, set->gbuf.p, set->h_large[s] ? 1 : 0};
+            dim3 grid(grid_of(ns, kLargeBlock), nc);
             hipError_t e;
             if constexpr (std::is_same<S, double>::value)
-                e = launch_large_adj64(mc, set->cur_form, grid, dim3(256), st, Afit, Aadj, L, set->abuf.as<double>());
+                e = launch_large_adj64(mc, set->cur_form, grid, dim3(kLargeBlock), st, Afit, Aadj, L,
+                                       set->abuf.as<double>());
             else
-                e = launch_large_adj32(mc, set->cur_form, grid, dim3(256), st, Afit, Aadj, L, set->abuf.as<float>());
+                e = launch_large_adj32(mc, set->cur_form, grid, dim3(kLargeBlock), st, Afit, Aadj, L,
+                                       set->abuf.as<float>());
             HIPCHECK(e);
         }
     }

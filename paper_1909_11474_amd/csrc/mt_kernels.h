@@ -610,11 +610,42 @@ __global__ __launch_bounds__(512) void k_adjoint(BArgs<S> A) {
 struct LArgs {
     int s, c0;                 // structure, first candidate of the chunk
     void* gbuf;                // [chunk][3][nbs] of S
+    // 1: the structure has one partial-sum slot per block (a structure over
+    // the batching limit); 0: one per wavefront (a batched structure sent to
+    // the two-pass path)
+    int per_block;
 };
+
+// Store a wavefront's group sums (lanes with (lane & 7) == 0 hold value vidx)
+// in the structure's partial-sum slots, values off + k for the k set in mask:
+// per wavefront (wavefronts past the structure, wave_in false, write
+// nothing), or per block, the block's wavefront sums added in wavefront order
+// through LDS.  Every thread of the block calls it; a wavefront with no atom
+// passes sum = 0 and vidx = (lane >> 3).
+__device__ __forceinline__ void large_store(const SetDev& d, const LArgs& L, double* __restrict__ partial,
+                                            int nv, int c, int la, bool wave_in, double sum, int vidx,
+                                            unsigned mask, int off, double (*sh)[8]) {
+    const int lane = threadIdx.x & 63;
+    if (!L.per_block) {
+        if (wave_in && (lane & 7) == 0 && ((mask >> vidx) & 1))
+            partial[((size_t)c * d.nslots + d.st_slot[L.s] + (la >> 6)) * nv + off + vidx] = sum;
+        return;
+    }
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((lane & 7) == 0) sh[w][vidx] = sum;
+    __syncthreads();
+    const int k = threadIdx.x;
+    if (k < 8 && ((mask >> k) & 1)) {
+        double t = sh[0][k];
+        for (int q = 1; q < nw; ++q) t += sh[q][k];
+        partial[((size_t)c * d.nslots + d.st_slot[L.s] + blockIdx.x) * nv + off + k] = t;
+    }
+    __syncthreads();
+}
 
 template <typename S, int M, bool E64, bool Full>
 __device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L, int la, int atom,
-                                               bool active) {
+                                               bool active, double& sum, int& vidx) {
     const SetDev& d = A.set;
     const int N = d.N;
     Geo<S, M> g;
@@ -657,14 +688,7 @@ __device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L
 #pragma unroll
     for (int k = 0; k < 6; ++k) v[1 + k] = active ? (double)w6[k] : 0.0;
     v[7] = 0.0;
-    int vidx;
-    const double sum = group_reduce8(v, 64, &vidx);
-    const int lane = threadIdx.x & 63;
-    // one slot per wavefront of the structure (inactive tail lanes included)
-    const int slot = d.st_slot[L.s] + (la >> 6);
-    // no partial sums when only the staged bond gradients are wanted
-    if (A.partial && (lane & 7) == 0 && vidx < 7)
-        A.partial[((size_t)c * d.nslots + slot) * A.nv + vidx] = sum;
+    sum = group_reduce8(v, 64, &vidx);
 }
 
 // E64: float64 energy terms (the float path's energy/force/virial mode).
@@ -677,10 +701,16 @@ __global__ __launch_bounds__(256) void k_large_site(BArgs<S> A, LArgs L) {
     const int atom = a0 + (active ? la : 0);
     const int Mi = active ? d.nnb[atom] : -1;
     const int Mw = wave_max_int(Mi);
-    if (Mw < 0) return;
-    dispatch_m<ClassLo<MC>::value, MC>(Mw, [&](auto mv) {
-        run_large_site<S, decltype(mv)::value, E64, Full>(A, L, la, atom, active);
-    });
+    __shared__ double sh[kLargeBlock / 64][8];
+    double sum = 0.0;
+    int vidx = (threadIdx.x & 63) >> 3;
+    if (Mw >= 0)
+        dispatch_m<ClassLo<MC>::value, MC>(Mw, [&](auto mv) {
+            run_large_site<S, decltype(mv)::value, E64, Full>(A, L, la, atom, active, sum, vidx);
+        });
+    // no partial sums when only the staged bond gradients are wanted
+    if (A.partial)
+        large_store(d, L, A.partial, A.nv, L.c0 + blockIdx.y, la, Mw >= 0, sum, vidx, 0x7f, 0, sh);
 }
 
 template <typename S, int MODE>
@@ -690,9 +720,11 @@ __global__ __launch_bounds__(256) void k_large_gather(BArgs<S> A, LArgs L) {
     const int a0 = d.st_off[L.s], Ns = d.st_off[L.s + 1] - a0;
     const int nbs = d.st_boff[L.s + 1] - d.st_boff[L.s];
     const int la = blockIdx.x * blockDim.x + threadIdx.x;
-    // wavefronts past the structure own no partial-sum slot (ceil(Ns / 64) slots)
-    if ((la & ~63) >= Ns) return;
+    // wavefronts past the structure own no per-wavefront slot; they still take
+    // part in a block's sums (with zeros)
+    const bool wave_in = (la & ~63) < Ns;
     const bool active = la < Ns;
+    __shared__ double sh[kLargeBlock / 64][8];
     const int atom = a0 + (active ? la : 0);
     const int c = L.c0 + blockIdx.y;
     const S* gb = reinterpret_cast<const S*>(L.gbuf) + (size_t)blockIdx.y * 3 * nbs;
@@ -728,8 +760,6 @@ __global__ __launch_bounds__(256) void k_large_gather(BArgs<S> A, LArgs L) {
     const int orig = active ? d.perm[atom] : 0;
     double v[8];
     for (int k = 0; k < 8; ++k) v[k] = 0.0;
-    const int lane = threadIdx.x & 63;
-    const int slot = d.st_slot[L.s] + (la >> 6);
     int vidx;
     if (MODE == MODE_FIT) {
         const S* fr = fref_of<S>(d);
@@ -738,7 +768,7 @@ __global__ __launch_bounds__(256) void k_large_gather(BArgs<S> A, LArgs L) {
             v[7] = (double)(ax * ax + ay * ay + az * az);
         }
         const double sum = group_reduce8(v, 64, &vidx);
-        if ((lane & 7) == 0 && vidx == 7) A.partial[((size_t)c * d.nslots + slot) * A.nv + 7] = sum;
+        large_store(d, L, A.partial, A.nv, c, la, wave_in, sum, vidx, 0x80, 0, sh);
     } else {
         if (active && A.vel) {
             const S vx = (S)A.vel[orig], vy = (S)A.vel[(size_t)N + orig], vz = (S)A.vel[(size_t)2 * N + orig];
@@ -747,7 +777,7 @@ __global__ __launch_bounds__(256) void k_large_gather(BArgs<S> A, LArgs L) {
             v[2] = (double)(wi[6] * vx + wi[7] * vy + wi[8] * vz);
         }
         const double sum = group_reduce8(v, 64, &vidx);
-        if ((lane & 7) == 0 && vidx < 3) A.partial[((size_t)c * d.nslots + slot) * A.nv + 8 + vidx] = sum;
+        large_store(d, L, A.partial, A.nv, c, la, wave_in, sum, vidx, 0x07, 8, sh);
         if (active && A.force) {
             double* f = A.force + (size_t)c * 3 * N;
             f[orig] = (double)Fx; f[(size_t)N + orig] = (double)Fy; f[(size_t)2 * N + orig] = (double)Fz;
@@ -794,7 +824,8 @@ __global__ __launch_bounds__(256) void k_large_residual(BArgs<S> A, LArgs L, S* 
 
 template <typename S, int M, bool Full>
 __device__ __forceinline__ void run_large_adjoint(const BArgs<S>& A, const LArgs& L, int la, int atom,
-                                                  bool active, int Ns, const S* __restrict__ abuf) {
+                                                  bool active, int Ns, const S* __restrict__ abuf,
+                                                  double& sum, int& vidx, double& sum2, int& vidx2) {
     const SetDev& d = A.set;
     const int N = d.N;
     constexpr int MM = M > 0 ? M : 1;
@@ -819,22 +850,16 @@ __device__ __forceinline__ void run_large_adjoint(const BArgs<S>& A, const LArgs
             return Vec4<S>{a[jm], a[Ns + jm], a[2 * Ns + jm], S(0)};
         },
         A.coef + ((size_t)c * d.S + L.s) * 8, phi);
-    const int lane = threadIdx.x & 63;
-    const int slot = d.st_slot[L.s] + (la >> 6);
     double v[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] = k < NX ? (double)phi[k < NX ? k : 0] : 0.0;
-    int vidx;
-    double sum = group_reduce8(v, 64, &vidx);
-    if ((lane & 7) == 0 && vidx < (NX < 8 ? NX : 8))
-        A.partial[((size_t)c * d.nslots + slot) * A.nv + vidx] = sum;
+    sum = group_reduce8(v, 64, &vidx);
     if constexpr (Full) {
         double u[8];
         u[0] = (double)phi[8];
 #pragma unroll
         for (int k = 1; k < 8; ++k) u[k] = 0.0;
-        sum = group_reduce8(u, 64, &vidx);
-        if ((lane & 7) == 0 && vidx == 0) A.partial[((size_t)c * d.nslots + slot) * A.nv + 8] = sum;
+        sum2 = group_reduce8(u, 64, &vidx2);
     }
 }
 
@@ -847,16 +872,26 @@ __global__ __launch_bounds__(256) void k_large_adjoint(BArgs<S> A, LArgs L, cons
     const int atom = a0 + (active ? la : 0);
     const int Mi = active ? d.nnb[atom] : -1;
     const int Mw = wave_max_int(Mi);
-    if (Mw < 0) return;                         // wavefronts past the structure own no slot
-    auto run = [&](auto mv) { run_large_adjoint<S, decltype(mv)::value, Full>(A, L, la, atom, active, Ns, abuf); };
-    if constexpr (MC <= 4) {
-        dispatch_m<0, MC>(Mw, run);
-    } else {
-        // two variants only: the dual passes of a wide variant take minutes to
-        // compile, and rows past the wave's coordination are padding bonds
-        if (Mw <= 8) run(std::integral_constant<int, 8>{});
-        else run(std::integral_constant<int, MC>{});
+    __shared__ double sh[kLargeBlock / 64][8];
+    double sum = 0.0, sum2 = 0.0;
+    int vidx = (threadIdx.x & 63) >> 3, vidx2 = vidx;
+    auto run = [&](auto mv) {
+        run_large_adjoint<S, decltype(mv)::value, Full>(A, L, la, atom, active, Ns, abuf, sum, vidx, sum2, vidx2);
+    };
+    if (Mw >= 0) {                              // a wavefront with no atom adds zeros
+        if constexpr (MC <= 4) {
+            dispatch_m<0, MC>(Mw, run);
+        } else {
+            // two variants only: the dual passes of a wide variant take minutes to
+            // compile, and rows past the wave's coordination are padding bonds
+            if (Mw <= 8) run(std::integral_constant<int, 8>{});
+            else run(std::integral_constant<int, MC>{});
+        }
     }
+    constexpr int NX = Form<Full>::nx;
+    const int c = L.c0 + blockIdx.y;
+    large_store(d, L, A.partial, A.nv, c, la, Mw >= 0, sum, vidx, (1u << (NX < 8 ? NX : 8)) - 1, 0, sh);
+    if constexpr (Full) large_store(d, L, A.partial, A.nv, c, la, Mw >= 0, sum2, vidx2, 0x01, 8, sh);
 }
 
 // Launchers, one per kernel family (defined in the mt_k_*.hip units).

@@ -624,7 +624,8 @@ int build_set(mt_set* set, const int64_t* atom_offset, const double* pos, const 
         set->max_atoms = std::max(set->max_atoms, ns);
         const bool large = set->h_large[s] != 0;
         const int npad = set->h_npad[s];
-        const int nsl = large ? (ns + 63) / 64 : std::max(1, npad / 64);
+        // over the batching limit: one slot per block of the two-pass kernels
+        const int nsl = large ? (ns + kLargeBlock - 1) / kLargeBlock : std::max(1, npad / 64);
         set->h_slot[s + 1] = set->h_slot[s] + nsl;
         if (large) ++set->n_large; else ++set->n_batched;
     }

@@ -948,5 +948,10 @@ hipError_t launch_large_adj32(int mc, int full, dim3 g, dim3 b, hipStream_t st, 
                               const BArgs<float>& Aadj, const LArgs& L, float* abuf);
 hipError_t launch_large_adj64(int mc, int full, dim3 g, dim3 b, hipStream_t st, const BArgs<double>& Afit,
                               const BArgs<double>& Aadj, const LArgs& L, double* abuf);
+// The Tersoff form's residual and dual-pass kernels of the two-pass gradient.
+hipError_t launch_large_adj32f(int mc, dim3 g, dim3 b, hipStream_t st, const BArgs<float>& A,
+                               const LArgs& L, float* abuf);
+hipError_t launch_large_adj64f(int mc, dim3 g, dim3 b, hipStream_t st, const BArgs<double>& A,
+                               const LArgs& L, double* abuf);
 
 }  // namespace mt

@@ -39,8 +39,19 @@ CFLAGS = [
 ]
 
 
+# Units that take longest to compile (minutes: the dual-number kernels for up
+# to sixteen neighbours); the parallel build starts them first.
+SLOW_UNITS = ("mt_k_large_adj32.hip", "mt_k_tf_large_adj32.hip", "mt_k_adj64.hip", "mt_k_tf_adj64.hip",
+              "mt_k_tf_adj32.hip", "mt_k_large_adj64.hip")
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+
+
+def _build_order(srcs):
+    rank = {u: k for k, u in enumerate(SLOW_UNITS)}
+    return sorted(srcs, key=lambda p: rank.get(os.path.basename(p), len(rank)))
 
 
 def _compile(src: str) -> str:
@@ -59,10 +70,11 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Compile every source and link the shared library; returns its path."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    srcs = sources()
+    srcs = _build_order(sources())
     workers = min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(max_workers=workers) as ex:
-        objs = list(ex.map(_compile, srcs))
+        done = dict(zip(srcs, ex.map(_compile, srcs)))
+    objs = [done[p] for p in sources()]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)

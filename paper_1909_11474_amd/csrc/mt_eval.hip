@@ -96,9 +96,8 @@ constexpr int kCoopSlots = 8;
 // wavefront totals in wavefront order finish the sums, so the order depends
 // only on the sizes.
 template <int NV>
-__device__ void coop_sums_n(const FinArgs& F, int c, int s, double* a, double (*sh)[256]) {
+__device__ void coop_sums_n(const FinArgs& F, int c, int s0, int s1, double* a, double (*sh)[256]) {
     const SetDev& d = F.set;
-    const int s0 = d.st_slot[s], s1 = d.st_slot[s + 1];
     const int nv = F.nv;                           // 8 or 16, a power of two
     const double* base = F.partial + ((size_t)c * d.nslots + s0) * nv;
     const int total = (s1 - s0) * nv;
@@ -133,8 +132,11 @@ __device__ void coop_sums_n(const FinArgs& F, int c, int s, double* a, double (*
 __device__ void coop_struct_sums(const FinArgs& F, int c, int s, double* e, double* w6, double* rf,
                                  double* j3, double (*sh)[256]) {
     double a[11];
-    if (F.nv >= 11) coop_sums_n<11>(F, c, s, a, sh);
-    else coop_sums_n<8>(F, c, s, a, sh);
+    const SetDev& d = F.set;
+    // a set of one structure owns every slot: no table lookup
+    const int s0 = d.S == 1 ? 0 : d.st_slot[s], s1 = d.S == 1 ? d.nslots : d.st_slot[s + 1];
+    if (F.nv >= 11) coop_sums_n<11>(F, c, s0, s1, a, sh);
+    else coop_sums_n<8>(F, c, s0, s1, a, sh);
     *e = a[0];
     for (int k = 0; k < 6; ++k) w6[k] = a[1 + k];
     *rf = a[7];
@@ -358,6 +360,20 @@ __global__ __launch_bounds__(256) void k_finalize_eval(FinArgs F) {
     const bool ok = cand_valid(F.x, c, F.full);
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
     double jacc[3] = {0, 0, 0};
+    if (d.S == 1) {
+        // one structure (a large cell): the whole block sums its slots, no
+        // slot-table reads and no block reduction of the heat current
+        double e, w6[6], rf, j3[3];
+        coop_struct_sums(F, c, 0, &e, w6, &rf, j3, sh);
+        if (threadIdx.x == 0) {
+            if (F.energy) F.energy[c] = ok ? e : nan;
+            if (F.virial)
+                for (int k = 0; k < 6; ++k) F.virial[(size_t)c * 6 + k] = ok ? w6[k] : nan;
+            if (F.heat)
+                for (int k = 0; k < 3; ++k) F.heat[3 * c + k] = ok ? j3[k] : nan;
+        }
+        return;
+    }
     for (int s = 0; F.coop && s < d.S; ++s) {
         if (!coop_struct(d, s)) continue;
         double e, w6[6], rf, j3[3];
@@ -927,7 +943,8 @@ static int launch_twopass_t(mt_set* set, const std::vector<int>& structs, int P,
         }
         for (int c0 = 0; c0 < P; c0 += chunk) {
             const int nc = std::min(chunk, P - c0);
-            LArgs L{s, c0, set->gbuf.p, set->h_large[s] ? 1 : 0};
+            LArgs L{s, c0, set->gbuf.p, set->h_large[s] ? 1 : 0, set->h_off[s], set->h_off[s + 1] - set->h_off[s],
+                    set->h_boff[s + 1] - set->h_boff[s], set->h_slot[s]};
             dim3 grid(grid_of(ns, kLargeBlock), nc);
             hipError_t e;
             if constexpr (std::is_same<S, double>::value)
@@ -1041,7 +1058,8 @@ static int launch_twopass_adjoint(mt_set* set, const std::vector<int>& structs, 
         }
         for (int c0 = 0; c0 < P; c0 += chunk) {
             const int nc = std::min(chunk, P - c0);
-            LArgs L{s, c0, set->gbuf.p, set->h_large[s] ? 1 : 0};
+            LArgs L{s, c0, set->gbuf.p, set->h_large[s] ? 1 : 0, set->h_off[s], set->h_off[s + 1] - set->h_off[s],
+                    set->h_boff[s + 1] - set->h_boff[s], set->h_slot[s]};
             dim3 grid(grid_of(ns, kLargeBlock), nc);
             hipError_t e;
             if constexpr (std::is_same<S, double>::value)

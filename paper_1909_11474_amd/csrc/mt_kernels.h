@@ -614,6 +614,9 @@ struct LArgs {
     // the batching limit); 0: one per wavefront (a batched structure sent to
     // the two-pass path)
     int per_block;
+    // the structure's first atom, atom count, bond count and first partial-sum
+    // slot, copied from the host tables so no kernel waits on reading them
+    int a0, ns, nbs, slot0;
 };
 
 // Store a wavefront's group sums (lanes with (lane & 7) == 0 hold value vidx)
@@ -628,7 +631,7 @@ __device__ __forceinline__ void large_store(const SetDev& d, const LArgs& L, dou
     const int lane = threadIdx.x & 63;
     if (!L.per_block) {
         if (wave_in && (lane & 7) == 0 && ((mask >> vidx) & 1))
-            partial[((size_t)c * d.nslots + d.st_slot[L.s] + (la >> 6)) * nv + off + vidx] = sum;
+            partial[((size_t)c * d.nslots + L.slot0 + (la >> 6)) * nv + off + vidx] = sum;
         return;
     }
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -638,7 +641,7 @@ __device__ __forceinline__ void large_store(const SetDev& d, const LArgs& L, dou
     if (k < 8 && ((mask >> k) & 1)) {
         double t = sh[0][k];
         for (int q = 1; q < nw; ++q) t += sh[q][k];
-        partial[((size_t)c * d.nslots + d.st_slot[L.s] + blockIdx.x) * nv + off + k] = t;
+        partial[((size_t)c * d.nslots + L.slot0 + blockIdx.x) * nv + off + k] = t;
     }
     __syncthreads();
 }
@@ -652,7 +655,7 @@ __device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L
     g.load(geom_of<S>(d), N, atom, active, &d.gd);
     constexpr int MM = M > 0 ? M : 1;
     const int c = L.c0 + blockIdx.y;
-    const int nbs = d.st_boff[L.s + 1] - d.st_boff[L.s];
+    const int nbs = L.nbs;
     const int Mi = active ? d.nnb[atom] : 0;
     const int lb = active ? d.lbo[atom] : 0;
     S rec[kNParam];
@@ -695,7 +698,7 @@ __device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L
 template <typename S, int MC, bool E64, bool Full = false>
 __global__ __launch_bounds__(256) void k_large_site(BArgs<S> A, LArgs L) {
     const SetDev& d = A.set;
-    const int a0 = d.st_off[L.s], Ns = d.st_off[L.s + 1] - a0;
+    const int a0 = L.a0, Ns = L.ns;
     const int la = blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = la < Ns;
     const int atom = a0 + (active ? la : 0);
@@ -717,8 +720,8 @@ template <typename S, int MODE>
 __global__ __launch_bounds__(256) void k_large_gather(BArgs<S> A, LArgs L) {
     const SetDev& d = A.set;
     const int N = d.N;
-    const int a0 = d.st_off[L.s], Ns = d.st_off[L.s + 1] - a0;
-    const int nbs = d.st_boff[L.s + 1] - d.st_boff[L.s];
+    const int a0 = L.a0, Ns = L.ns;
+    const int nbs = L.nbs;
     const int la = blockIdx.x * blockDim.x + threadIdx.x;
     // wavefronts past the structure own no per-wavefront slot; they still take
     // part in a block's sums (with zeros)
@@ -801,8 +804,8 @@ template <typename S>
 __global__ __launch_bounds__(256) void k_large_residual(BArgs<S> A, LArgs L, S* __restrict__ abuf) {
     const SetDev& d = A.set;
     const int N = d.N;
-    const int a0 = d.st_off[L.s], Ns = d.st_off[L.s + 1] - a0;
-    const int nbs = d.st_boff[L.s + 1] - d.st_boff[L.s];
+    const int a0 = L.a0, Ns = L.ns;
+    const int nbs = L.nbs;
     const int la = blockIdx.x * blockDim.x + threadIdx.x;
     if (la >= Ns) return;
     const int atom = a0 + la;
@@ -866,7 +869,7 @@ __device__ __forceinline__ void run_large_adjoint(const BArgs<S>& A, const LArgs
 template <typename S, int MC, bool Full>
 __global__ __launch_bounds__(256) void k_large_adjoint(BArgs<S> A, LArgs L, const S* __restrict__ abuf) {
     const SetDev& d = A.set;
-    const int a0 = d.st_off[L.s], Ns = d.st_off[L.s + 1] - a0;
+    const int a0 = L.a0, Ns = L.ns;
     const int la = blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = la < Ns;
     const int atom = a0 + (active ? la : 0);

@@ -944,7 +944,7 @@ static int launch_twopass_t(mt_set* set, const std::vector<int>& structs, int P,
         for (int c0 = 0; c0 < P; c0 += chunk) {
             const int nc = std::min(chunk, P - c0);
             LArgs L{s, c0, set->gbuf.p, set->h_large[s] ? 1 : 0, set->h_off[s], set->h_off[s + 1] - set->h_off[s],
-                    set->h_boff[s + 1] - set->h_boff[s], set->h_slot[s]};
+                    set->h_boff[s + 1] - set->h_boff[s], set->h_slot[s], set->h_kmax[s]};
             dim3 grid(grid_of(ns, kLargeBlock), nc);
             hipError_t e;
             if constexpr (std::is_same<S, double>::value)
@@ -1059,7 +1059,7 @@ static int launch_twopass_adjoint(mt_set* set, const std::vector<int>& structs, 
         for (int c0 = 0; c0 < P; c0 += chunk) {
             const int nc = std::min(chunk, P - c0);
             LArgs L{s, c0, set->gbuf.p, set->h_large[s] ? 1 : 0, set->h_off[s], set->h_off[s + 1] - set->h_off[s],
-                    set->h_boff[s + 1] - set->h_boff[s], set->h_slot[s]};
+                    set->h_boff[s + 1] - set->h_boff[s], set->h_slot[s], set->h_kmax[s]};
             dim3 grid(grid_of(ns, kLargeBlock), nc);
             hipError_t e;
             if constexpr (std::is_same<S, double>::value)

@@ -33,8 +33,13 @@ static hipError_t launch_large_pair(int mc, int mode, int full, dim3 g, dim3 b, 
                               : launch_large_form<S, false>(mc, mode, g, b, st, A, L);
     if (e != hipSuccess) return e;
     if (mode == MODE_STAGE) return hipGetLastError();
-    if (mode == MODE_FIT) hipLaunchKernelGGL((k_large_gather<S, MODE_FIT>), g, b, 0, st, A, L);
-    else hipLaunchKernelGGL((k_large_gather<S, MODE_EVAL>), g, b, 0, st, A, L);
+    if (mc == 4) {
+        if (mode == MODE_FIT) hipLaunchKernelGGL((k_large_gather<S, MODE_FIT, 4>), g, b, 0, st, A, L);
+        else hipLaunchKernelGGL((k_large_gather<S, MODE_EVAL, 4>), g, b, 0, st, A, L);
+    } else {
+        if (mode == MODE_FIT) hipLaunchKernelGGL((k_large_gather<S, MODE_FIT, 16>), g, b, 0, st, A, L);
+        else hipLaunchKernelGGL((k_large_gather<S, MODE_EVAL, 16>), g, b, 0, st, A, L);
+    }
     return hipGetLastError();
 }
 

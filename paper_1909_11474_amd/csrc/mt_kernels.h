@@ -614,9 +614,10 @@ struct LArgs {
     // the batching limit); 0: one per wavefront (a batched structure sent to
     // the two-pass path)
     int per_block;
-    // the structure's first atom, atom count, bond count and first partial-sum
-    // slot, copied from the host tables so no kernel waits on reading them
-    int a0, ns, nbs, slot0;
+    // the structure's first atom, atom count, bond count, first partial-sum
+    // slot and largest coordination, copied from the host tables so no kernel
+    // waits on reading them
+    int a0, ns, nbs, slot0, kmax;
 };
 
 // Store a wavefront's group sums (lanes with (lane & 7) == 0 hold value vidx)
@@ -648,11 +649,11 @@ __device__ __forceinline__ void large_store(const SetDev& d, const LArgs& L, dou
 
 template <typename S, int M, bool E64, bool Full>
 __device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L, int la, int atom,
-                                               bool active, double& sum, int& vidx) {
+                                               bool active, double& sum, int& vidx, int rows = M) {
     const SetDev& d = A.set;
     const int N = d.N;
     Geo<S, M> g;
-    g.load(geom_of<S>(d), N, atom, active, &d.gd);
+    g.load(geom_of<S>(d), N, atom, active, &d.gd, rows);
     constexpr int MM = M > 0 ? M : 1;
     const int c = L.c0 + blockIdx.y;
     const int nbs = L.nbs;
@@ -702,21 +703,31 @@ __global__ __launch_bounds__(256) void k_large_site(BArgs<S> A, LArgs L) {
     const int la = blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = la < Ns;
     const int atom = a0 + (active ? la : 0);
-    const int Mi = active ? d.nnb[atom] : -1;
-    const int Mw = wave_max_int(Mi);
     __shared__ double sh[kLargeBlock / 64][8];
     double sum = 0.0;
     int vidx = (threadIdx.x & 63) >> 3;
-    if (Mw >= 0)
-        dispatch_m<ClassLo<MC>::value, MC>(Mw, [&](auto mv) {
-            run_large_site<S, decltype(mv)::value, E64, Full>(A, L, la, atom, active, sum, vidx);
-        });
+    bool wave_in;
+    if constexpr (MC <= 4) {
+        // one variant for the class: the geometry rows (up to the structure's
+        // largest coordination) are read without first waiting for the
+        // wavefront's bond counts
+        wave_in = (la & ~63) < Ns;
+        if (wave_in) run_large_site<S, MC, E64, Full>(A, L, la, atom, active, sum, vidx, L.kmax);
+    } else {
+        const int Mi = active ? d.nnb[atom] : -1;
+        const int Mw = wave_max_int(Mi);
+        wave_in = Mw >= 0;
+        if (wave_in)
+            dispatch_m<ClassLo<MC>::value, MC>(Mw, [&](auto mv) {
+                run_large_site<S, decltype(mv)::value, E64, Full>(A, L, la, atom, active, sum, vidx);
+            });
+    }
     // no partial sums when only the staged bond gradients are wanted
     if (A.partial)
-        large_store(d, L, A.partial, A.nv, L.c0 + blockIdx.y, la, Mw >= 0, sum, vidx, 0x7f, 0, sh);
+        large_store(d, L, A.partial, A.nv, L.c0 + blockIdx.y, la, wave_in, sum, vidx, 0x7f, 0, sh);
 }
 
-template <typename S, int MODE>
+template <typename S, int MODE, int MC>
 __global__ __launch_bounds__(256) void k_large_gather(BArgs<S> A, LArgs L) {
     const SetDev& d = A.set;
     const int N = d.N;
@@ -732,32 +743,32 @@ __global__ __launch_bounds__(256) void k_large_gather(BArgs<S> A, LArgs L) {
     const int c = L.c0 + blockIdx.y;
     const S* gb = reinterpret_cast<const S*>(L.gbuf) + (size_t)blockIdx.y * 3 * nbs;
     const GeomArrays<S> G = geom_of<S>(d);
+    // The reverse-bond indices (rows up to the structure's largest
+    // coordination) are read in the same memory round trip as the atom's
+    // bond count; the staged gradients of its bonds in the next.
+    const int rows = L.kmax < MC ? L.kmax : MC;
+    int rv[MC];
+#pragma unroll
+    for (int m = 0; m < MC; ++m) rv[m] = active && m < rows ? d.revc[(size_t)m * N + atom] : 0;
+    const int Mi = active ? d.nnb[atom] : 0, lb = active ? d.lbo[atom] : 0;
     S Fx = S(0), Fy = S(0), Fz = S(0);
     S wi[9];
     for (int k = 0; k < 9; ++k) wi[k] = S(0);
-    if (active) {
-        const int Mi = d.nnb[atom], lb = d.lbo[atom];
-        // every bond's reverse index first, then every staged gradient: two
-        // dependent memory round trips per atom instead of two per bond
-        int rv[MT_MAX_NBR];
 #pragma unroll
-        for (int m = 0; m < MT_MAX_NBR; ++m) rv[m] = m < Mi ? d.revc[(size_t)m * N + atom] : 0;
-#pragma unroll
-        for (int m = 0; m < MT_MAX_NBR; ++m) {
-            if (m >= Mi) break;
-            const size_t o = (size_t)m * N + atom;
-            const int r = rv[m];
-            const S rx = gb[r], ry = gb[nbs + r], rz = gb[2 * nbs + r];
-            Fx += gb[lb + m] - rx;
-            Fy += gb[nbs + lb + m] - ry;
-            Fz += gb[2 * nbs + lb + m] - rz;
-            if (MODE == MODE_EVAL) {
-                const S rr = G.rhi[o];
-                const S dx = rr * G.ux[o], dy = rr * G.uy[o], dz = rr * G.uz[o];
-                wi[0] += dx * rx; wi[1] += dx * ry; wi[2] += dx * rz;
-                wi[3] += dy * rx; wi[4] += dy * ry; wi[5] += dy * rz;
-                wi[6] += dz * rx; wi[7] += dz * ry; wi[8] += dz * rz;
-            }
+    for (int m = 0; m < MC; ++m) {
+        if (m >= Mi) break;
+        const size_t o = (size_t)m * N + atom;
+        const int r = rv[m];
+        const S rx = gb[r], ry = gb[nbs + r], rz = gb[2 * nbs + r];
+        Fx += gb[lb + m] - rx;
+        Fy += gb[nbs + lb + m] - ry;
+        Fz += gb[2 * nbs + lb + m] - rz;
+        if (MODE == MODE_EVAL) {
+            const S rr = G.rhi[o];
+            const S dx = rr * G.ux[o], dy = rr * G.uy[o], dz = rr * G.uz[o];
+            wi[0] += dx * rx; wi[1] += dx * ry; wi[2] += dx * rz;
+            wi[3] += dy * rx; wi[4] += dy * ry; wi[5] += dy * rz;
+            wi[6] += dz * rx; wi[7] += dz * ry; wi[8] += dz * rz;
         }
     }
     const int orig = active ? d.perm[atom] : 0;

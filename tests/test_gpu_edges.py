@@ -9,6 +9,7 @@ import pytest
 
 import workloads as W
 from oracle import tersoff as T
+from oracle.neighbors import neighbor_list_set
 
 pytestmark = pytest.mark.gpu
 
@@ -185,6 +186,61 @@ def test_one_large_structure_set(api, precision):
         assert np.abs(o1["F"][c] - o2["F"][c, :600]).max() <= 1e-12 * np.abs(o2["F"][c, :600]).max()
     ts1.close()
     ts2.close()
+
+
+def honeycomb_sheet(nx, ny, b=2.4, vacuum=20.0):
+    """Periodic honeycomb sheet of nx * ny rectangular cells (4 atoms each,
+    bond b): every atom has exactly three neighbours within R2 (the second
+    shell is at sqrt(3) b = 4.16 A)."""
+    r3 = np.sqrt(3.0) * b
+    basis = np.array([[0.0, 0.0, 0.0], [r3 / 2, b / 2, 0.0], [r3 / 2, 1.5 * b, 0.0], [0.0, 2 * b, 0.0]])
+    grid = np.array([[i * r3, j * 3 * b, 0.0] for i in range(nx) for j in range(ny)])
+    pos = (grid[:, None, :] + basis[None]).reshape(-1, 3) + [0.0, 0.0, vacuum / 2]
+    return pos, np.diag([nx * r3, ny * 3 * b, vacuum])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_large_structures_below_four_neighbours(api, precision):
+    """Two-pass structures of the four-neighbour class whose atoms have fewer
+    than four bonds: a 1,024-atom honeycomb sheet (largest coordination 3,
+    below the class's four geometry rows) and an 800-site diamond block with
+    three vacancies (atoms of three and four bonds in one wavefront).  E, F, W,
+    W_i and J against the oracle, fitness and dZ/dx against its autograd."""
+    g = rng(90)
+    hc = honeycomb_sheet(8, 32)
+    pos, cell = W.diamond(5, 5, 4)
+    keep = np.setdiff1d(np.arange(len(pos)), g.choice(len(pos), 3, replace=False))
+    s = W.make_set([hc, (W.displace(g, pos[keep], 0.03), cell)])
+    ts = api.from_structures(s)
+    st = ts.stats()
+    assert st["n_large"] == 2 and st["max_coordination"] == 4
+    counts = np.bincount(neighbor_list_set(s, R2)[0], minlength=s.n_atoms)
+    assert counts[:1024].max() == 3 and counts[:1024].min() == 3
+    assert counts[1024:].min() == 3 and counts[1024:].max() == 4
+    X = W.draw_params(rng(91), 2)
+    vel = rng(92).normal(0.0, 0.01, size=(s.n_atoms, 3))
+    out = ts.tersoff_eval(X, precision=precision, atom_virial=True, velocities=vel)
+    E, F, Wv, Wi, J = (out[k].cpu().numpy() for k in ("E", "F", "W", "Wi", "J"))
+    n = s.sizes().astype(float)
+    for c, x in enumerate(X):
+        ref = T.evaluate_set(s, x, R1, R2, atom_virial=True, velocities=vel)
+        if precision == "fp64":
+            for got, want in ((E[c], ref["E"]), (F[c], ref["F"]), (Wv[c], ref["W6"]), (Wi[c], ref["Wi"]),
+                              (J[c], ref["J"])):
+                assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
+        else:
+            assert np.abs(E[c] / n - ref["E"] / n).max() <= 1e-6
+            assert np.abs(F[c] - ref["F"]).max() <= 1e-4
+            assert np.abs(Wv[c] / n[:, None] - ref["W6"] / n[:, None]).max() <= 1e-5
+            assert np.abs(Wi[c] - ref["Wi"]).max() <= 1e-4
+            assert np.abs(J[c] - ref["J"]).max() <= 1e-5 * np.abs(ref["J"]).max()
+    refs = T.reference_data(s, W.draw_params(rng(93), 1)[0], R1, R2)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    Z = ts.fitness(X, precision=precision).cpu().numpy()
+    Zo = T.fitness(s, X, refs, topology=T.topology(s, R2))
+    assert np.abs(Z - Zo).max() <= (1e-10 if precision == "fp64" else 1e-5) * np.abs(Zo).max()
+    check_grad(ts, s, X[:1], refs, precision)
+    ts.close()
 
 
 def test_graph_replay_after_the_staging_buffer_grows(api):

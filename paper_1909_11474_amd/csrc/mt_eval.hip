@@ -899,7 +899,7 @@ int time_class_launches(mt_set* set, const LaunchCfg& cfg, int P, int precision,
 // Candidates per launch of the two-pass path for structure s: bounded so that
 // the bond-gradient staging buffer stays within 256 MB.
 static int twopass_chunk(const mt_set* set, int s, int P, size_t elem) {
-    const size_t per = 3 * (size_t)(set->h_boff[s + 1] - set->h_boff[s]) * elem;
+    const size_t per = 4 * (size_t)(set->h_boff[s + 1] - set->h_boff[s]) * elem;
     const size_t chunk = std::min<size_t>((size_t)P, (256ull << 20) / std::max<size_t>(per, 1));
     return (int)std::min<size_t>(std::max<size_t>(chunk, 1), 65535);
 }
@@ -908,7 +908,7 @@ int reserve_twopass(mt_set* set, const ItemPlan* plan, int P, int precision) {
     const size_t elem = precision == MT_FP64 ? sizeof(double) : sizeof(float);
     size_t need = 0;
     auto add = [&](int s) {
-        const size_t per = 3 * (size_t)(set->h_boff[s + 1] - set->h_boff[s]) * elem;
+        const size_t per = 4 * (size_t)(set->h_boff[s + 1] - set->h_boff[s]) * elem;
         need = std::max(need, per * twopass_chunk(set, s, P, elem));
     };
     for (int s = 0; s < set->S; ++s)
@@ -935,7 +935,7 @@ static int launch_twopass_t(mt_set* set, const std::vector<int>& structs, int P,
     for (int s : structs) {
         const int mc = set->h_kmax[s] <= 4 ? 4 : 16;
         const int ns = set->h_off[s + 1] - set->h_off[s];
-        const size_t per = 3 * (size_t)(set->h_boff[s + 1] - set->h_boff[s]) * sizeof(S);
+        const size_t per = 4 * (size_t)(set->h_boff[s + 1] - set->h_boff[s]) * sizeof(S);
         const int chunk = twopass_chunk(set, s, P, sizeof(S));
         if (set->gbuf.bytes < per * chunk) {
             set_error("two-pass staging buffer not reserved");
@@ -1050,7 +1050,7 @@ static int launch_twopass_adjoint(mt_set* set, const std::vector<int>& structs, 
     for (int s : structs) {
         const int mc = set->h_kmax[s] <= 4 ? 4 : 16;
         const int ns = set->h_off[s + 1] - set->h_off[s];
-        const size_t per = 3 * (size_t)(set->h_boff[s + 1] - set->h_boff[s]) * sizeof(S);
+        const size_t per = 4 * (size_t)(set->h_boff[s + 1] - set->h_boff[s]) * sizeof(S);
         const int chunk = twopass_chunk(set, s, P, sizeof(S));
         if (set->gbuf.bytes < per * chunk || set->abuf.bytes < 3 * (size_t)ns * sizeof(S) * chunk) {
             set_error("two-pass staging buffers not reserved");

@@ -607,9 +607,23 @@ __global__ __launch_bounds__(512) void k_adjoint(BArgs<S> A) {
 // energy/virial partials; pass 2 gathers forces, per-atom virial, heat
 // current and the force residual.
 // ---------------------------------------------------------------------------
+// One staged bond gradient of the two-pass path: x, y, z and an unused
+// fourth value, so that the gather reads a partner's reverse bond with one
+// vector load (one cache line) instead of three scattered ones.
+template <typename S>
+struct Stage4;
+template <>
+struct Stage4<float> {
+    using T = float4;
+};
+template <>
+struct Stage4<double> {
+    using T = double4;
+};
+
 struct LArgs {
     int s, c0;                 // structure, first candidate of the chunk
-    void* gbuf;                // [chunk][3][nbs] of S
+    void* gbuf;                // [chunk][nbs] of Stage4<S> (x, y, z, unused)
     // 1: the structure has one partial-sum slot per block (a structure over
     // the batching limit); 0: one per wavefront (a batched structure sent to
     // the two-pass path)
@@ -668,15 +682,12 @@ __device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L
     // about one wavefront per SIMD for a large structure: the bonds' float64
     // energy chains interleave
     site_eval<S, S, M, E64, Full, false>(g, p, U, Gx, Gy, Gz);
-    S* gb = reinterpret_cast<S*>(L.gbuf) + (size_t)blockIdx.y * 3 * nbs;
+    using V4 = typename Stage4<S>::T;
+    V4* gb = reinterpret_cast<V4*>(L.gbuf) + (size_t)blockIdx.y * nbs;
     if (active) {
 #pragma unroll
         for (int m = 0; m < M; ++m)
-            if (m < Mi) {
-                gb[lb + m] = Gx[m];
-                gb[nbs + lb + m] = Gy[m];
-                gb[2 * nbs + lb + m] = Gz[m];
-            }
+            if (m < Mi) gb[lb + m] = V4{Gx[m], Gy[m], Gz[m], S(0)};
     }
     S w6[6];
 #pragma unroll
@@ -741,7 +752,8 @@ __global__ __launch_bounds__(256) void k_large_gather(BArgs<S> A, LArgs L) {
     __shared__ double sh[kLargeBlock / 64][8];
     const int atom = a0 + (active ? la : 0);
     const int c = L.c0 + blockIdx.y;
-    const S* gb = reinterpret_cast<const S*>(L.gbuf) + (size_t)blockIdx.y * 3 * nbs;
+    using V4 = typename Stage4<S>::T;
+    const V4* gb = reinterpret_cast<const V4*>(L.gbuf) + (size_t)blockIdx.y * nbs;
     const GeomArrays<S> G = geom_of<S>(d);
     // The reverse-bond indices (rows up to the structure's largest
     // coordination) are read in the same memory round trip as the atom's
@@ -759,10 +771,11 @@ __global__ __launch_bounds__(256) void k_large_gather(BArgs<S> A, LArgs L) {
         if (m >= Mi) break;
         const size_t o = (size_t)m * N + atom;
         const int r = rv[m];
-        const S rx = gb[r], ry = gb[nbs + r], rz = gb[2 * nbs + r];
-        Fx += gb[lb + m] - rx;
-        Fy += gb[nbs + lb + m] - ry;
-        Fz += gb[2 * nbs + lb + m] - rz;
+        const V4 rg = gb[r], og = gb[lb + m];
+        const S rx = rg.x, ry = rg.y, rz = rg.z;
+        Fx += og.x - rx;
+        Fy += og.y - ry;
+        Fz += og.z - rz;
         if (MODE == MODE_EVAL) {
             const S rr = G.rhi[o];
             const S dx = rr * G.ux[o], dy = rr * G.uy[o], dz = rr * G.uz[o];
@@ -820,14 +833,16 @@ __global__ __launch_bounds__(256) void k_large_residual(BArgs<S> A, LArgs L, S* 
     const int la = blockIdx.x * blockDim.x + threadIdx.x;
     if (la >= Ns) return;
     const int atom = a0 + la;
-    const S* gb = reinterpret_cast<const S*>(L.gbuf) + (size_t)blockIdx.y * 3 * nbs;
+    using V4 = typename Stage4<S>::T;
+    const V4* gb = reinterpret_cast<const V4*>(L.gbuf) + (size_t)blockIdx.y * nbs;
     S Fx = S(0), Fy = S(0), Fz = S(0);
     const int Mi = d.nnb[atom], lb = d.lbo[atom];
     for (int m = 0; m < Mi; ++m) {
         const int r = d.revc[(size_t)m * N + atom];
-        Fx += gb[lb + m] - gb[r];
-        Fy += gb[nbs + lb + m] - gb[nbs + r];
-        Fz += gb[2 * nbs + lb + m] - gb[2 * nbs + r];
+        const V4 rg = gb[r], og = gb[lb + m];
+        Fx += og.x - rg.x;
+        Fy += og.y - rg.y;
+        Fz += og.z - rg.z;
     }
     const S* fr = fref_of<S>(d);
     S* a = abuf + (size_t)blockIdx.y * 3 * Ns;

@@ -64,6 +64,7 @@ mt::SetDev mt_set::dev() const {
     const double* g = gd.as<double>();
     d.gd = GeomArrays<double>{g, g + KN, g + 2 * KN, g + 3 * KN, nullptr, g + 4 * KN,
                               g + 5 * KN, g + 6 * KN, nullptr, nullptr};
+    d.gcs = gcs.as<float>();
     d.fref32 = fref32.as<float>();
     d.fref64 = fref64.as<double>();
     return d;

@@ -113,8 +113,14 @@ struct SetDev {
     const int* jl;                              // [kcap][N] structure-local neighbour atom
     GeomArrays<float> gf;
     GeomArrays<double> gd;
+    // [15][N] cos(theta_jk) of the bond pairs j < k < 6, pair k (k - 1) / 2 + j:
+    // float64 unit-vector products rounded once (zero for padding bonds)
+    const float* gcs;
     const float* fref32;  const double* fref64; // [3][N] sorted order
 };
+
+// Pairs of bonds whose cos(theta) the pair table holds (bonds 0-5).
+constexpr int kCosPairs = 15;
 
 // ---------------------------------------------------------------------------
 // Device math.  float: the hardware transcendental instructions (v_exp_f32,

@@ -118,6 +118,7 @@ struct mt_set {
     mt::DevBuf gf, gd;                       // float / double geometry, 8 resp. 7 arrays of [kcap][N]
     mt::DevBuf gf_rlo;                       // float low part of r, [kcap][N]
     mt::DevBuf gpk;                          // float geometry packed as 2 x float4, [2][kcap][N]
+    mt::DevBuf gcs;                          // cos(theta) of bond pairs j < k < 6, [15][N] float
 
     // references (sorted order)
     bool has_ref = false;

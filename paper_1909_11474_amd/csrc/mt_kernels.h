@@ -250,7 +250,7 @@ __device__ __forceinline__ void run_batched(const BArgs<S>& A, const Item& it, c
     const S* __restrict__ pbuf = reinterpret_cast<const S*>(lds);
     Vec4<S>* __restrict__ xb = reinterpret_cast<Vec4<S>*>(lds + lds_param_bytes<S>(it.nc));
     Geo<S, M> g;
-    g.load(geom_of<S>(d), N, x.atom, x.active, &d.gd);
+    g.load(geom_of<S>(d), N, x.atom, x.active, d.gcs);
     constexpr int MM = M > 0 ? M : 1;
     int rv[MM];
 #pragma unroll
@@ -667,7 +667,7 @@ __device__ __forceinline__ void run_large_site(const BArgs<S>& A, const LArgs& L
     const SetDev& d = A.set;
     const int N = d.N;
     Geo<S, M> g;
-    g.load(geom_of<S>(d), N, atom, active, &d.gd, rows);
+    g.load(geom_of<S>(d), N, atom, active, d.gcs, rows);
     constexpr int MM = M > 0 ? M : 1;
     const int c = L.c0 + blockIdx.y;
     const int nbs = L.nbs;

@@ -325,6 +325,29 @@ __global__ void k_struct_tables(const int* __restrict__ st_off, const int* __res
     }
 }
 
+// cos(theta_jk) of every pair of the first six bond slots of a sorted atom, the
+// float64 unit vectors' product rounded once to float (pair k (k - 1) / 2 + j;
+// zero where a slot is past the capacity, and padding slots have zero unit
+// vectors).  The float kernels read their cached angle cosines from here.
+__global__ void k_pair_cos(int N, int kcap, const double* __restrict__ gd, float* __restrict__ gcs) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= N) return;
+    const size_t KN = (size_t)kcap * N;
+    double vx[6], vy[6], vz[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        const bool ok = m < kcap;
+        vx[m] = ok ? gd[(size_t)m * N + a] : 0.0;
+        vy[m] = ok ? gd[KN + (size_t)m * N + a] : 0.0;
+        vz[m] = ok ? gd[2 * KN + (size_t)m * N + a] : 0.0;
+    }
+#pragma unroll
+    for (int k = 1; k < 6; ++k)
+#pragma unroll
+        for (int j = 0; j < k; ++j)
+            gcs[(size_t)(k * (k - 1) / 2 + j) * N + a] = (float)(vx[j] * vx[k] + vy[j] * vy[k] + vz[j] * vz[k]);
+}
+
 // Bond geometry for every (sorted atom, slot).  Padded slots (m >= coordination)
 // get f_C = f_C' = 0 and a zero unit vector, so they add nothing anywhere.
 __global__ void k_geometry(int N, int S, int kcap, double R1, double R2,
@@ -641,6 +664,7 @@ int build_set(mt_set* set, const int64_t* atom_offset, const double* pos, const 
     HIPCHECK(set->gf_rlo.reserve(sizeof(float) * KN));
     HIPCHECK(set->gpk.reserve(sizeof(float4) * 2 * KN));
     HIPCHECK(set->gd.reserve(sizeof(double) * 7 * KN));
+    HIPCHECK(set->gcs.reserve(sizeof(float) * kCosPairs * (size_t)N));
     HIPCHECK(set->rev.reserve(sizeof(int) * KN));
     HIPCHECK(set->revc.reserve(sizeof(int) * KN));
     HIPCHECK(set->jl.reserve(sizeof(int) * KN));
@@ -654,6 +678,8 @@ int build_set(mt_set* set, const int64_t* atom_offset, const double* pos, const 
         set->gf.as<float>(), set->gf_rlo.as<float>(), set->gpk.as<float4>(),
         set->gd.as<double>(), set->rev.as<int>(), set->revc.as<int>(), set->jl.as<int>(), set->nbr_j.as<int>(),
         set->nbr_sh.as<int>(), flags.as<int>());
+    HIPCHECK(hipGetLastError());
+    k_pair_cos<<<grid_of(N, 256), 256, 0, st>>>(N, kcap, set->gd.as<double>(), set->gcs.as<float>());
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipMemcpyAsync(&hflags, flags.p, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
@@ -677,6 +703,8 @@ int update_geometry(mt_set* set, const double* pos, hipStream_t st) {
         set->gf.as<float>(), set->gf_rlo.as<float>(), set->gpk.as<float4>(),
         set->gd.as<double>(), set->rev.as<int>(), set->revc.as<int>(), set->jl.as<int>(), set->nbr_j.as<int>(),
         set->nbr_sh.as<int>(), B.flags.as<int>());
+    HIPCHECK(hipGetLastError());
+    k_pair_cos<<<grid_of(N, 256), 256, 0, st>>>(N, kcap, set->gd.as<double>(), set->gcs.as<float>());
     HIPCHECK(hipGetLastError());
     return MT_OK;
 }

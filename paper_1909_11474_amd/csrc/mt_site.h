@@ -54,14 +54,14 @@ struct Geo {
         }
     }
 
-    // G64 (float geometry only): the float64 unit vectors, from which the cached
-    // cos(theta) values are formed and rounded once; from float unit vectors
-    // they carry up to ~2e-7 absolute error, which zeta passes on to the
-    // energy through (cos - h)^2.
+    // Gcs (float geometry only): the set's pair table of cos(theta) values,
+    // formed from the float64 unit vectors and rounded once; from float unit
+    // vectors they carry up to ~2e-7 absolute error, which zeta passes on to
+    // the energy through (cos - h)^2.
     // rows: neighbour rows the arrays hold (a variant wider than the set's
     // capacity reads the rows past it as padding bonds)
     __device__ __forceinline__ void load(const GeomArrays<S>& G, int N, int atom, bool active,
-                                         const GeomArrays<double>* G64 = nullptr, int rows = M) {
+                                         const float* Gcs = nullptr, int rows = M) {
         if constexpr (sizeof(S) == 4) {
             if (G.pk0) {
 #pragma unroll
@@ -74,22 +74,14 @@ struct Geo {
                     rlo[m] = b.x; rinv[m] = b.y; fc[m] = b.z; hfcp[m] = b.w;
                 }
                 if constexpr (kCache && NP > 0) {
-                    if (G64 && active) {
-                        double vx[M], vy[M], vz[M];
-#pragma unroll
-                        for (int m = 0; m < M; ++m) {
-                            const size_t o = (size_t)m * N + atom;
-                            const bool ok = m < rows;
-                            vx[m] = ok ? G64->ux[o] : 0.0;
-                            vy[m] = ok ? G64->uy[o] : 0.0;
-                            vz[m] = ok ? G64->uz[o] : 0.0;
-                        }
+                    static_assert(M <= 6, "the pair table holds bonds 0-5");
+                    if (Gcs && active) {
                         int p = 0;
 #pragma unroll
                         for (int j = 0; j < M; ++j)
 #pragma unroll
                             for (int k = j + 1; k < M; ++k)
-                                cs[p++] = (S)(vx[j] * vx[k] + vy[j] * vy[k] + vz[j] * vz[k]);
+                                cs[p++] = k < rows ? Gcs[(size_t)(k * (k - 1) / 2 + j) * N + atom] : S(0);
                         return;
                     }
                 }

@@ -59,9 +59,9 @@ PMC_TRAFFIC = {
     "sources": ["paper_1909_11474_amd/csrc/mt_common.h", "paper_1909_11474_amd/csrc/mt_site.h",
                 "paper_1909_11474_amd/csrc/mt_kernels.h", "paper_1909_11474_amd/csrc/mt_k_fit32.hip",
                 "paper_1909_11474_amd/csrc/mt_eval.hip"],
-    "sha256_16": "fcccbb7de480d88b",
-    "fetch_bytes": 43584.3 * 1024 * 2.00,
-    "write_bytes": 34705.4 * 1024 * 1.00,
+    "sha256_16": "54c629f3af175721",
+    "fetch_bytes": 38901.1 * 1024 * 2.00,
+    "write_bytes": 39072.1 * 1024 * 1.00,
 }
 
 

@@ -6,6 +6,8 @@ Tolerances (float64): 20 steps of 1 fs on a thermal 64-atom cell, positions
 1e-9 A, velocities 1e-10 A/fs, energies 1e-9 eV (rounding differences grow
 slowly over a short chaotic trajectory); momentum 1e-10 u A/fs.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -217,3 +219,43 @@ def test_run_with_look_ahead_equals_single_steps(MDm):
     assert a.rebuilds == b.rebuilds and a.rebuilds > 0
     a.close()
     b.close()
+
+
+def test_float_path_after_position_updates(MDm):
+    """The float path's geometry tables (packed bonds and the angle-cosine pair
+    table) follow both kinds of position update: after mt_set_update_positions
+    the float32 results equal those of a set built at the new positions bit for
+    bit; after mt_set_update_geometry (0.5 A skin, atoms moved 0.02 A) they meet
+    the float32 bar against the oracle (1e-6 eV/atom, 1e-4 eV/A, 1e-5 eV/atom
+    virial)."""
+    import torch
+    from paper_1909_11474_amd import api, _lib as L
+    from oracle import tersoff as T
+    wl = W.config2(n_struct=4, pop=3)
+    s = wl.structs
+    g = rng(120)
+    pos1 = W.displace(g, s.pos, 0.05)
+    ts = api.from_structures(s)
+    s1 = W.make_set([(pos1[s.offset[k]:s.offset[k + 1]], s.cell[k]) for k in range(s.n_struct)])
+    fresh = api.from_structures(s1)
+    p1 = torch.as_tensor(pos1.T.copy(), device="cuda").contiguous()
+    L.check(ts._lib.mt_set_update_positions(ts._handle, ctypes_ptr(p1), None), "update")
+    a = ts.tersoff_eval(wl.population, precision="fp32")
+    b = fresh.tersoff_eval(wl.population, precision="fp32")
+    for k in ("E", "F", "W"):
+        assert torch.equal(a[k], b[k]), k
+    fresh.close()
+    L.check(ts._lib.mt_set_list_skin(ts._handle, ctypes.c_double(0.5), None), "skin")
+    pos2 = W.displace(g, pos1, 0.02)
+    p2 = torch.as_tensor(pos2.T.copy(), device="cuda").contiguous()
+    L.check(ts._lib.mt_set_update_geometry(ts._handle, ctypes_ptr(p2), None), "geometry")
+    out = ts.tersoff_eval(wl.population, precision="fp32")
+    E, F, Wv = (out[k].cpu().numpy() for k in ("E", "F", "W"))
+    s2 = W.make_set([(pos2[s.offset[k]:s.offset[k + 1]], s.cell[k]) for k in range(s.n_struct)])
+    n = s2.sizes().astype(float)
+    for c, x in enumerate(wl.population):
+        ref = T.evaluate_set(s2, x, 2.8, 3.2)
+        assert np.abs(E[c] / n - ref["E"] / n).max() <= 1e-6
+        assert np.abs(F[c] - ref["F"]).max() <= 1e-4
+        assert np.abs(Wv[c] / n[:, None] - ref["W6"] / n[:, None]).max() <= 1e-5
+    ts.close()

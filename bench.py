@@ -52,16 +52,17 @@ TUNED_SHAPES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1
 # uneven workload) from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB
 # per dispatch) scaled by what the same counters read for a 256 MiB
 # device-to-device copy (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00), recorded in
-# profiles/k_batched_fit32_uneven_500x300.md.  Valid only for the kernel sources
-# and the host file that places the work items (mt_eval.hip) it was measured
-# on: reported when their hash still matches.
+# profiles/k_batched_fit32_uneven_500x300.md.  Valid only for the kernel sources,
+# the host file that places the work items (mt_eval.hip) and the build script
+# (per-unit code-generation flags) it was measured on: reported when their hash
+# still matches.
 PMC_TRAFFIC = {
     "sources": ["paper_1909_11474_amd/csrc/mt_common.h", "paper_1909_11474_amd/csrc/mt_site.h",
                 "paper_1909_11474_amd/csrc/mt_kernels.h", "paper_1909_11474_amd/csrc/mt_k_fit32.hip",
-                "paper_1909_11474_amd/csrc/mt_eval.hip"],
-    "sha256_16": "54c629f3af175721",
-    "fetch_bytes": 38901.1 * 1024 * 2.00,
-    "write_bytes": 39072.1 * 1024 * 1.00,
+                "paper_1909_11474_amd/csrc/mt_eval.hip", "paper_1909_11474_amd/build.py"],
+    "sha256_16": "86920f9757d52e06",
+    "fetch_bytes": 38831.7 * 1024 * 2.00,
+    "write_bytes": 42297.9 * 1024 * 1.00,
 }
 
 

@@ -39,6 +39,15 @@ CFLAGS = [
 ]
 
 
+# Per-unit code generation: LLVM's memory-clause scheduling strategy for the
+# float fitness and gradient kernels of the minimal form and the float fitness
+# kernels of the Tersoff form, chosen by same-box timing (uneven generation
+# -2 %, uneven gradient -1.5 %, GA batch -1.3 %, Tersoff-form GA batch -2 %;
+# the Tersoff-form gradient units were 2-3 % slower with it and keep the
+# default).  It changes instruction order only: results are bit-identical.
+UNIT_FLAGS = {u: ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause"]
+              for u in ("mt_k_fit32.hip", "mt_k_fitr32.hip", "mt_k_adj32.hip", "mt_k_tf_fit32.hip")}
+
 # Units that take longest to compile (minutes: the dual-number kernels for up
 # to sixteen neighbours); the parallel build starts them first.
 SLOW_UNITS = ("mt_k_large_adj32.hip", "mt_k_tf_large_adj32.hip", "mt_k_adj64.hip", "mt_k_tf_adj64.hip",
@@ -57,7 +66,7 @@ def _build_order(srcs):
 def _compile(src: str) -> str:
     import time
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *UNIT_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     t0 = time.perf_counter()
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:

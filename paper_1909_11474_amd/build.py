@@ -47,6 +47,8 @@ CFLAGS = [
 # default).  It changes instruction order only: results are bit-identical.
 UNIT_FLAGS = {u: ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause"]
               for u in ("mt_k_fit32.hip", "mt_k_fitr32.hip", "mt_k_adj32.hip", "mt_k_tf_fit32.hip")}
+UNIT_FLAGS["mt_k_fit32.hip"] += ["-mllvm", "-amdgpu-use-amdgpu-trackers=1"]
+UNIT_FLAGS["mt_k_fit32_m4.hip"] = ["-mllvm", "-amdgpu-sched-strategy=iterative-minreg"]
 
 # Units that take longest to compile (minutes: the dual-number kernels for up
 # to sixteen neighbours); the parallel build starts them first.

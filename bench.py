@@ -60,9 +60,9 @@ PMC_TRAFFIC = {
     "sources": ["paper_1909_11474_amd/csrc/mt_common.h", "paper_1909_11474_amd/csrc/mt_site.h",
                 "paper_1909_11474_amd/csrc/mt_kernels.h", "paper_1909_11474_amd/csrc/mt_k_fit32.hip",
                 "paper_1909_11474_amd/csrc/mt_eval.hip", "paper_1909_11474_amd/build.py"],
-    "sha256_16": "86920f9757d52e06",
-    "fetch_bytes": 38831.7 * 1024 * 2.00,
-    "write_bytes": 42297.9 * 1024 * 1.00,
+    "sha256_16": "514a5b8796fceaa5",
+    "fetch_bytes": 38379.6 * 1024 * 2.00,
+    "write_bytes": 23094.7 * 1024 * 1.00,
 }
 
 

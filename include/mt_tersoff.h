@@ -341,8 +341,9 @@ int mt_md_max_disp(int N, const double* pos, const double* ref, double* out, voi
  * rate of a burst of back-to-back calls.  When cache_path is not NULL every
  * timing is appended to that text file as a comment line ("# ...") and the
  * choice as a line "<set key> | block=B tile=T persistent=0|1 graph=0|1 ms=..";
- * a matching entry already there is used without timing.  Calls that overlap
- * on one set race (the set's workspace is shared).
+ * a matching entry already there is used without timing (MT_EINVAL if its
+ * shape is out of range: block a multiple of 64 up to 512, tile >= 0).  Calls
+ * that overlap on one set race (the set's workspace is shared).
  */
 int mt_autotune(mt_set* set, int P, int precision, const char* cache_path);
 

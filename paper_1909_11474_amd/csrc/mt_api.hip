@@ -581,6 +581,12 @@ int mt_autotune(mt_set* set, int P, int precision, const char* cache_path) {
             LaunchCfg c;
             const int nread = sscanf(line.c_str() + bar + 3, "block=%d tile=%d persistent=%d graph=%d",
                                      &c.block, &c.tile, &c.persistent, &c.graph);
+            // the batched kernels are compiled for at most 512 threads per
+            // block, in whole wavefronts
+            if (nread >= 3 && (c.block < 64 || c.block > 512 || c.block % 64 != 0 || c.tile < 0 ||
+                               (c.persistent != 0 && c.persistent != 1) || (c.graph != 0 && c.graph != 1)))
+                return fail(MT_EINVAL, "cache entry holds an invalid launch shape (block: a multiple of 64 "
+                                       "up to 512; tile >= 0; persistent and graph 0 or 1)");
             if (nread >= 3 && get_plan(set, P, c, fam)) {
                 set->tuned[{P, precision}] = c;
                 clear_graphs(set);

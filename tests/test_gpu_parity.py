@@ -7,6 +7,7 @@ Tolerances (GPU vs oracle):
   |dF| <= 1e-4 eV/A per component, |dw_s| <= 1e-5 eV/atom (virial per atom).
 """
 import ctypes
+import time
 
 import numpy as np
 import pytest
@@ -221,6 +222,25 @@ def test_launch_shapes_give_identical_fitness(api, tmp_path, precision):
     ts.close()
 
 
+def test_cached_launch_shape_out_of_range_is_rejected(api, tmp_path):
+    """A cache entry whose shape the batched kernels cannot run (more than 512
+    threads per block, or not whole wavefronts) is refused on the host with
+    MT_EINVAL before anything is launched; the set keeps working."""
+    from paper_1909_11474_amd import _lib as L
+    wl, refs = small_training(4)
+    ts = api.from_structures(wl.structs)
+    ts.attach_reference(refs["e"], refs["w"], refs["f"])
+    X = wl.population
+    P = X.shape[0]
+    Z0 = ts.fitness(X, precision="fp64").cpu().numpy()
+    for k, block in enumerate((1024, 96, 0)):
+        with pytest.raises(L.MTError) as e:
+            _force_cfg(ts, P, "fp64", tmp_path / f"bad{k}.txt", block, 8, 0)
+        assert e.value.code == L.MT_EINVAL
+    assert np.array_equal(ts.fitness(X, precision="fp64").cpu().numpy(), Z0)
+    ts.close()
+
+
 def test_repeated_graph_replays_are_identical(api):
     """Graph replays of the same generation give the same Z every time, and a
     replay picks up new parameter values written into the bound buffer."""
@@ -286,6 +306,13 @@ def test_per_launch_kernel_timing(api):
     ts = api.from_structures(s)
     ts.attach_reference(refs["e"], refs["w"], refs["f"])
     X = torch.as_tensor(W.draw_params(np.random.Generator(np.random.PCG64(84)), 40), device="cuda")
+    # an idle GPU needs a moment of work to reach its clock: without it the
+    # first timed launches (the per-launch pass) run slow and the two
+    # timings disagree
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 0.3:
+        ts.fitness(X, precision="fp32")
+        torch.cuda.synchronize()
     launches, sl = ts.profile_fitness_launches(X, "fp32", 8)
     classes = sorted(mc for _, mc in launches)
     assert classes[0] == 4 and classes[-1] > 4
